@@ -1,0 +1,218 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself (brute force, a library routine, a closed form, an invariant), chosen so
+that a dropped term, a wrong sign, a shifted index or a transposed operand
+fails at least one of them (the mutation tests at the end demonstrate that)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_12280_amd import datagen
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = max(np.max(np.abs(b)), 1e-300)
+    return float(np.max(np.abs(a - b)) / den)
+
+
+def brute_force(x, taps, tap_len):
+    """Pure-Python triple loop of Eq. (1) on tiny inputs."""
+    n = len(x)
+    out = []
+    for t in range(len(taps)):
+        row = []
+        for i in range(n):
+            acc = 0j
+            for k in range(int(tap_len[t])):
+                if i - k >= 0:
+                    acc += complex(x[i - k]) * complex(taps[t][k])
+            row.append(acc)
+        out.append(row)
+    return np.array(out, dtype=np.complex128)
+
+
+@pytest.mark.parametrize("seed,n,m,k", [(1, 17, 1, 1), (2, 40, 3, 9), (3, 64, 2, 7), (4, 5, 3, 9)])
+def test_brute_force(seed, n, m, k):
+    x, bank = datagen.random_case(seed, n, m, k)
+    ref = brute_force(x, bank.taps, bank.tap_len)
+    got = oracle.conv(x, bank.taps, bank.tap_len)
+    assert rel_err(got, ref) <= 1e-12
+    p = oracle.power(x, bank.taps, bank.tap_len)
+    assert rel_err(p, np.abs(ref) ** 2) <= 1e-12
+
+
+def test_numpy_convolve_toy_full(toy):
+    """Every row at the 9 x 2^16 toy size equals numpy.convolve(x, h_t)[:N]."""
+    x = toy.x.astype(np.complex128)
+    y = oracle.conv(toy.x, toy.bank.taps, toy.bank.tap_len)
+    for t in range(toy.bank.num_templates):
+        h = toy.bank.taps[t, : toy.bank.tap_len[t]].astype(np.complex128)
+        ref = np.convolve(x, h)[: x.shape[0]]
+        assert rel_err(y[t], ref) <= 1e-12
+
+
+def test_impulse_returns_template():
+    """x = delta[j - j0]: y_t[i] = h_t[i - j0] for 0 <= i - j0 < K_t, else 0 (bitwise)."""
+    _, bank = datagen.random_case(11, 8, 4, 13)
+    n, j0 = 80, 23
+    x = np.zeros(n, dtype=np.complex64)
+    x[j0] = 1.0
+    y = oracle.conv(x, bank.taps, bank.tap_len)
+    for t in range(bank.num_templates):
+        expect = np.zeros(n, dtype=np.complex128)
+        kt = int(bank.tap_len[t])
+        expect[j0: j0 + kt] = bank.taps[t, :kt].astype(np.complex128)
+        assert np.array_equal(y[t], expect)
+
+
+def test_linearity():
+    x1, bank = datagen.random_case(21, 300, 3, 17)
+    x2, _ = datagen.random_case(22, 300, 3, 17)
+    a, b = 0.7 - 1.3j, -2.1 + 0.4j
+    xs = a * x1.astype(np.complex128) + b * x2.astype(np.complex128)
+    lhs = oracle.conv(xs, bank.taps, bank.tap_len)
+    rhs = a * oracle.conv(x1, bank.taps, bank.tap_len) + b * oracle.conv(x2, bank.taps, bank.tap_len)
+    assert rel_err(lhs, rhs) <= 1e-12
+
+
+def test_convolution_theorem():
+    """Eq. (2): x*h = IFFT(FFT(x) . FFT(h)) with zero padding to >= N+K-1."""
+    x, bank = datagen.random_case(31, 1000, 4, 33)
+    y = oracle.conv(x, bank.taps, bank.tap_len)
+    nfft = 2048
+    fx = np.fft.fft(x.astype(np.complex128), nfft)
+    for t in range(bank.num_templates):
+        ref = np.fft.ifft(fx * np.fft.fft(bank.taps[t].astype(np.complex128), nfft))[:1000]
+        assert rel_err(y[t], ref) <= 1e-10
+
+
+def test_full_linear_tail():
+    """Outputs past N continue the full linear convolution (N + K - 1 points)."""
+    x, bank = datagen.random_case(32, 50, 2, 9, ragged=False)
+    y = oracle.conv(x, bank.taps, bank.tap_len, i0=0, i1=58)
+    for t in range(2):
+        ref = np.convolve(x.astype(np.complex128), bank.taps[t].astype(np.complex128))
+        assert rel_err(y[t], ref) <= 1e-12
+
+
+def test_window_and_sampled_points_agree():
+    x, bank = datagen.random_case(33, 5000, 5, 40)
+    full = oracle.power(x, bank.taps, bank.tap_len)
+    win = oracle.power(x, bank.taps, bank.tap_len, rows=[3, 1], i0=1234, i1=4321)
+    assert np.array_equal(win[0], full[3, 1234:4321])
+    assert np.array_equal(win[1], full[1, 1234:4321])
+    rng = np.random.default_rng(0)
+    t = rng.integers(0, 5, 200)
+    i = rng.integers(0, 5000, 200)
+    pts = oracle.power_at(x, bank.taps, bank.tap_len, t, i)
+    assert rel_err(pts, full[t, i]) <= 1e-13
+
+
+def test_thread_count_does_not_change_result():
+    x, bank = datagen.random_case(34, 20000, 3, 30)
+    a = oracle.power(x, bank.taps, bank.tap_len, nthreads=1)
+    b = oracle.power(x, bank.taps, bank.tap_len, nthreads=4)
+    assert np.array_equal(a, b)
+
+
+def test_zero_template_row_is_input_power(toy):
+    """The z = 0 template is a delta at k = 8, so its row of the power plane is
+    |x[i-8]|^2 (the input row of the filter-output plane), 0 for i < 8."""
+    t0 = int(np.nonzero(toy.bank.z == 0)[0][0])
+    p = oracle.power(toy.x, toy.bank.taps, toy.bank.tap_len, rows=[t0])[0]
+    xa = np.abs(toy.x.astype(np.complex128)) ** 2
+    ref = np.zeros_like(p)
+    ref[8:] = xa[:-8]
+    assert rel_err(p, ref) <= 1e-12
+
+
+# --- transforms ------------------------------------------------------------
+
+@pytest.mark.parametrize("L", [8, 64, 1024])
+def test_dft_matches_numpy_fft(L):
+    rng = np.random.default_rng(L)
+    x = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    assert rel_err(oracle.dft(x, -1), np.fft.fft(x)) <= 1e-12
+    assert rel_err(oracle.dft(x, +1), np.fft.ifft(x) * L) <= 1e-12
+
+
+def test_dft_closed_forms():
+    L = 256
+    d = np.zeros(L, complex)
+    d[5] = 1
+    q = np.arange(L)
+    assert rel_err(oracle.dft(d), np.exp(-2j * np.pi * 5 * q / L)) <= 1e-13
+    c = oracle.dft(np.ones(L))
+    assert abs(c[0] - L) < 1e-9 and np.max(np.abs(c[1:])) < 1e-9
+    x = np.random.default_rng(1).standard_normal(L) + 0j
+    assert abs(np.sum(np.abs(oracle.dft(x)) ** 2) / L - np.sum(np.abs(x) ** 2)) < 1e-8
+
+
+@pytest.mark.parametrize("L", [64, 1024, 2048])
+def test_template_spectrum(L):
+    _, bank = datagen.random_case(41, 4, 2, 33)
+    for t in range(2):
+        h = bank.taps[t, : bank.tap_len[t]]
+        ref = np.fft.fft(h.astype(np.complex128), L) / L
+        assert rel_err(oracle.template_spectrum(h, L), ref) <= 1e-12
+
+
+# --- Alg. 2 and Alg. 1 -----------------------------------------------------
+
+@pytest.mark.parametrize("L,n,k_max", [(64, 1000, 9), (1024, 5000, 33), (2048, 9000, 101),
+                                       (4096, 13000, 101), (8192, 20000, 421), (64, 57, 9)])
+def test_overlap_save_equals_direct(L, n, k_max):
+    x, bank = datagen.random_case(50 + L, n, 3, k_max)
+    v, s = oracle.ols_geometry(n, k_max, L)
+    assert v == L - k_max + 1 and s == math.ceil(n / v)
+    y_ols = oracle.ols_convolve(x, bank.taps, bank.tap_len, L)
+    y_dir = oracle.conv(x, bank.taps, bank.tap_len)
+    assert rel_err(y_ols, y_dir) <= 1e-10
+
+
+def test_overlap_save_prefix():
+    """A shorter input (n < planned length) is the prefix problem on its own."""
+    x, bank = datagen.random_case(60, 3000, 2, 21)
+    y = oracle.ols_convolve(x[:2100], bank.taps, bank.tap_len, 256)
+    assert rel_err(y, oracle.conv(x[:2100], bank.taps, bank.tap_len)) <= 1e-10
+
+
+@pytest.mark.parametrize("k_sub", [8, 64])
+def test_overlap_add_equals_direct(k_sub):
+    x, bank = datagen.random_case(70 + k_sub, 3000, 1, 101, ragged=False)
+    y = oracle.ola_convolve(x, bank.taps[0], k_sub)
+    assert rel_err(y, oracle.conv(x, bank.taps)[0]) <= 1e-12
+
+
+# --- candidates ----------------------------------------------------------
+
+def test_topk_order_and_ties():
+    p = np.array([[1.0, 5.0, 3.0], [5.0, 2.0, 5.0]])
+    got = oracle.topk(p, 4)
+    assert got == [(0, 1, 5.0), (1, 0, 5.0), (1, 2, 5.0), (0, 2, 3.0)]
+    rng = np.random.default_rng(3)
+    q = rng.random((7, 50))
+    ref = sorted(((t, i, q[t, i]) for t in range(7) for i in range(50)), key=lambda c: (-c[2], c[0], c[1]))
+    assert oracle.topk(q, 16) == ref[:16]
+
+
+# --- planted mistakes: each plausible oracle error fails a pin ------------
+
+def test_mutations_are_caught():
+    x, bank = datagen.random_case(80, 48, 2, 7, ragged=False)
+    ref = brute_force(x, bank.taps, bank.tap_len)
+    good = oracle.conv(x, bank.taps, bank.tap_len)
+    assert rel_err(good, ref) <= 1e-12
+    dropped = bank.tap_len.copy()
+    dropped[0] -= 1                                  # a dropped tap
+    assert rel_err(oracle.conv(x, bank.taps, dropped), ref) > 1e-3
+    assert rel_err(oracle.conv(x, np.conj(bank.taps), bank.tap_len), ref) > 1e-3   # sign of Im
+    assert rel_err(oracle.conv(x, bank.taps[:, ::-1], bank.tap_len), ref) > 1e-3   # reversed taps
+    shifted = np.concatenate([[0], x[:-1]])          # off-by-one alignment
+    assert rel_err(oracle.conv(shifted, bank.taps, bank.tap_len), ref) > 1e-3
+    # the wrong row of the bank (rows transposed) is caught too
+    assert rel_err(oracle.conv(x, bank.taps[::-1], bank.tap_len), ref) > 1e-3
+    assert rel_err(oracle.ols_convolve(x, bank.taps, None, 16)[:, 1:], ref[:, :-1]) > 1e-3
