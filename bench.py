@@ -1,0 +1,211 @@
+"""Throughput of the FT-convolution hot path on one MI355X.
+
+One step = one fdas_convolve call: overlap-save FDFIR of one 2^22-point
+complex64 spectrum against 85 templates (z = -42..42, 17..101 taps), segment
+transform L = 2048, writing the 85 x 2^22 float32 power plane.  The input
+and the output plane are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  Extra legs: the direct TDFIR baseline on the
+same workload, and the FP64 CPU oracle timed on a bounded sample of the same
+workload (which also gives a parity figure for the sampled rows).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "template-samples/s (85 tpl x 2^22 pts) + HBM roofline frac; served p50/p99 ms"
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector (packed)
+KERNEL_SOURCES = ("paper_1805_12280_amd/csrc/seg_fft.h", "paper_1805_12280_amd/csrc/fdas_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fdfir_fused_ska-85x2^22_L2048_traffic.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; None otherwise."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def algorithmic_bytes(n, m, L):
+    """Bytes the method itself must move: the input once, the power plane once
+    and the pre-transformed templates once."""
+    return 8 * n + 4 * m * n + 8 * m * L
+
+
+def nominal_flops(n, m, L, k_max):
+    v = L - (k_max - 1)
+    s = math.ceil(n / v)
+    fft = 5 * L * math.log2(L)
+    return s * (m * (fft + 6 * L + 3 * v) + fft)
+
+
+def time_calls(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def cpu_baseline_leg(w, P_gpu_rows_fn, target_s: float):
+    """FP64 oracle on all 85 templates over a prefix of the outputs, sized to
+    take about target_s of wall time on the host's cores."""
+    import numpy as np
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from fdas_check import PlaneStats
+    threads = oracle.threads()
+    m = w.bank.num_templates
+    # calibrate on a short prefix
+    t0 = time.perf_counter()
+    cal = 1 << 14
+    oracle.power(w.x, w.bank.taps, w.bank.tap_len, i1=cal)
+    rate = m * cal / max(time.perf_counter() - t0, 1e-6)
+    n_s = int(min(w.n, max(cal, (rate * target_s / m) // 4096 * 4096)))
+    t0 = time.perf_counter()
+    ref = oracle.power(w.x, w.bank.taps, w.bank.tap_len, i1=n_s)
+    wall = time.perf_counter() - t0
+    st = PlaneStats()
+    st.add(list(range(m)), P_gpu_rows_fn(n_s), ref)
+    del np
+    return {
+        "value": m * n_s / wall, "unit": "template-samples/s", "cores": threads, "kind": "oracle",
+        "sample": f"all {m} templates x first {n_s} of {w.n} outputs (FP64 direct, C + OpenMP), "
+                  f"{wall:.1f} s wall",
+    }, {"rows": m, "outputs": n_s, "norm_err": st.norm_err, "rrmse": st.rrmse}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seg-fft", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tdfir", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling PMC byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the FT convolution here has no multi-GPU path "
+              "(a spectrum or a template group per GPU would need no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_12280_amd import datagen, fdas
+
+    if not os.path.exists(fdas.LIB_PATH):
+        from paper_1805_12280_amd import build
+        build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)    # 1 GiB
+        dst = torch.empty_like(src)
+        ms = time_calls(torch, lambda: dst.copy_(src), 5, 2)
+        log(f"copy probe: 1 GiB read + 1 GiB write, {ms:.3f} ms, {2 * 2**30 / ms / 1e6:.1f} GB/s")
+        return
+
+    log("generating the 85 x 2^22 workload ...")
+    w = datagen.ska_workload()
+    m, n, L, k_max = w.bank.num_templates, w.n, args.seg_fft, w.bank.k_max
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=L)
+    x = torch.from_numpy(w.x).to(dev)
+    out = torch.empty((m, n), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    log(f"plan: {plan.info.as_dict()} variant={plan.variant}")
+
+    ms = time_calls(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup)
+    value = m * n / (ms * 1e-3)
+    abytes = algorithmic_bytes(n, m, L)
+    achieved = abytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    log(f"fdas_convolve: {ms:.4f} ms/step, {value:.4e} template-samples/s, {achieved:.1f} GB/s")
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "template-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded complex Gaussian noise + 3 chirps at amplitude-SNR 8; "
+                "85 chirp templates z=-42..42)",
+        "config": {"workload": w.name, "templates": m, "n": n, "k_max": k_max,
+                   "taps_total": int(w.bank.tap_len.sum()), "seg_fft": L,
+                   "path": "overlap-save FDFIR + |y|^2, one fused launch"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "nominal_tflops": nominal_flops(n, m, L, k_max) / (ms * 1e-3) / 1e12,
+    }
+
+    if not args.no_tdfir:
+        td_steps = max(2, min(args.steps, 5))
+        td_ms = time_calls(torch, lambda: plan.tdfir(x, out=out), td_steps, 1)
+        td_flops = 8.0 * int(w.bank.tap_len.sum()) * n
+        result["tdfir"] = {"ms_per_step": td_ms, "value": m * n / (td_ms * 1e-3),
+                           "unit": "template-samples/s",
+                           "tflops": td_flops / (td_ms * 1e-3) / 1e12,
+                           "frac_fp32_vector_peak": td_flops / (td_ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+        log(f"fdas_tdfir: {td_ms:.3f} ms/step")
+        plan.convolve(x, out=out)          # leave the FDFIR plane in `out`
+        torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        log("CPU oracle leg ...")
+        cpu, parity = cpu_baseline_leg(w, lambda ns: out[:, :ns].cpu().numpy(), args.cpu_seconds)
+        result["cpu_baseline"] = cpu
+        result["parity_sample"] = parity
+        log(f"cpu oracle: {cpu['value']:.3e} template-samples/s on {cpu['cores']} threads; "
+            f"parity on sample: {parity}")
+
+    print(json.dumps(result), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * fdas.h -- C ABI of libfdas.so: FT convolution of one complex spectrum with
+ * a bank of complex FIR templates, with the spectral power of every output,
+ * on an MI355X (gfx950).
+ *
+ * What is computed (Section 3 of Wang, Thiagaraj & Sinnen, "FPGA-based
+ * Acceleration of FT Convolution for Pulsar Search Using OpenCL"):
+ * for each template t < M and output i < n,
+ *
+ *     y_t[i] = sum_{k < K_t} x[i-k] * h_t[k]      (Section 3.1, Eq. (1);
+ *                                                  x[j] = 0 for j < 0)
+ *     P_t[i] = Re(y_t[i])^2 + Im(y_t[i])^2        (power, Section 4.3)
+ *
+ * fdas_convolve reaches P by overlap-save on the input (Section 3.2.2,
+ * Alg. 2): segments of L = seg_fft points overlapping by K_max-1, one forward
+ * FFT per segment shared by all templates, a pointwise product with the
+ * pre-transformed templates, an inverse FFT per (segment, template), the
+ * first K_max-1 points of each discarded, and |y|^2 written.  fdas_tdfir
+ * evaluates Eq. (1) directly, with the taps processed in blocks (overlap-add
+ * on the taps, Section 3.1.2, Alg. 1).  Both write the same plane.
+ *
+ * Conventions for every call:
+ *  - Complex numbers are interleaved float32 pairs (re, im) ("complex64").
+ *  - "device" pointers are HIP device memory of the plan's device; "host"
+ *    pointers are ordinary host memory.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that take a stream only enqueue work on it and return without
+ *    waiting, unless stated otherwise.
+ *  - Every call returns an fdas status; nothing aborts, throws across the
+ *    ABI or prints.  A failing call leaves its output buffers unspecified and
+ *    records detail text for fdas_last_error().
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    FDAS_OK = 0,
+    FDAS_EINVAL = 1,        /* NULL pointer, size out of range, misalignment,
+                               unsupported seg_fft */
+    FDAS_ENOMEM = 2,        /* plan would not fit in free device memory, or a
+                               device allocation failed */
+    FDAS_EHIP = 3,          /* a HIP runtime call failed; see fdas_last_error */
+    FDAS_EUNSUPPORTED = 4   /* flag or precision this library does not build */
+};
+
+/* ---- plan flags -------------------------------------------------------- */
+#define FDAS_FP32            0u          /* float32 storage and arithmetic */
+#define FDAS_TAPS_ON_DEVICE  (1u << 0)   /* `taps` and `tap_len` are device pointers */
+
+typedef struct fdas_plan fdas_plan;
+
+typedef struct {
+    int32_t seg_fft;          /* L: points per segment transform */
+    int32_t valid_per_seg;    /* V = L - (K_max - 1): outputs kept per segment */
+    int64_t num_segments;     /* S = ceil(input_len / V) */
+    int32_t k_max;            /* K_max */
+    int32_t num_templates;    /* M */
+    int64_t input_len;        /* largest n accepted by fdas_convolve/fdas_tdfir */
+    int64_t resident_bytes;   /* device memory the plan holds */
+    int32_t threads_per_fft;  /* work-items per segment transform (L / 16) */
+    int32_t fused_grid;       /* workgroups of one fdas_convolve launch at input_len */
+    int32_t variant;          /* kernel variant id (see fdas_variant_name) */
+    int32_t device;           /* HIP device ordinal the plan lives on */
+} fdas_plan_info_t;
+
+/*
+ * fdas_plan_create -- validate a template bank, copy it to the device and
+ * build the pre-transformed template spectra (Alg. 2: the coefficient array
+ * is Fourier transformed once, ahead of the segments).
+ *
+ *   out        receives the plan (host pointer to a pointer; not NULL).
+ *   taps       complex64 [M][K_max], row-major, zero-padded beyond
+ *              tap_len[t]; host memory, or device memory with
+ *              FDAS_TAPS_ON_DEVICE.  Copied: the caller may free it on return.
+ *   tap_len    int32 [M], each in [0, K_max]; NULL means every row has K_max
+ *              taps.  Same memory kind as taps.
+ *   M          templates, >= 1.
+ *   K_max      taps per row of `taps`, >= 1 and <= seg_fft / 2.
+ *   input_len  largest input length the plan will be given, >= 1.
+ *   seg_fft    L in {1024, 2048, 4096}, or 0 for the default 2048.
+ *   flags      FDAS_FP32, optionally | FDAS_TAPS_ON_DEVICE; anything else
+ *              returns FDAS_EUNSUPPORTED.
+ *   hip_stream stream on which the plan is built; the call waits for that
+ *              work before it returns, so the plan is ready on any stream.
+ *
+ * The template spectra H_t[q] = (1/L) sum_k h_t[k] exp(-2 pi i q k / L) are
+ * computed in float64 on the device and rounded once to complex64; the 1/L
+ * of the inverse transform is folded into them.  The plan owns all device
+ * memory it allocates; fdas_plan_destroy frees it.
+ * Errors: FDAS_EINVAL (NULL out/taps, M < 1, K_max < 1, K_max > L/2,
+ * tap_len out of range, input_len < 1, seg_fft not supported),
+ * FDAS_EUNSUPPORTED, FDAS_ENOMEM (checked against free device memory before
+ * allocating), FDAS_EHIP.  On error *out is set to NULL.
+ */
+int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *tap_len,
+                     int32_t M, int32_t K_max, int64_t input_len, int32_t seg_fft,
+                     uint32_t flags, void *hip_stream);
+
+/*
+ * fdas_convolve -- the overlap-save FDFIR hot path (Alg. 2 with the power
+ * of Section 4.3), one launch for all M templates.
+ *
+ *   plan       from fdas_plan_create (not NULL).
+ *   d_in       device complex64 [n], 8-byte aligned.
+ *   n          1 <= n <= input_len.
+ *   d_power    device float32, M rows of ld_power floats, 4-byte aligned;
+ *              row t receives P_t[0..n).  Columns n..ld_power-1 are not
+ *              written.
+ *   ld_power   row stride in floats, >= n.
+ *   hip_stream stream to enqueue on.
+ *
+ * Asynchronous: returns after enqueueing; the caller keeps d_in and d_power
+ * alive until the stream has run the work.  The plan is read-only here, so
+ * one plan may be used from several streams at once.
+ * Errors: FDAS_EINVAL (NULL or misaligned pointers, n or ld_power out of
+ * range), FDAS_EHIP (launch failure).
+ */
+int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
+                  int64_t ld_power, void *hip_stream);
+
+/*
+ * fdas_tdfir -- direct time-domain FIR (Section 3.1, Eq. (1)), taps taken in
+ * blocks and accumulated (overlap-add on the taps, Alg. 1), with the same
+ * power output.  Arguments, output contract and errors as fdas_convolve.
+ */
+int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
+               int64_t ld_power, void *hip_stream);
+
+/*
+ * fdas_segment_fft -- the plan's L-point segment transform on its own,
+ * in natural order, for `count` independent transforms (the FFT engine role
+ * of Section 4.2).
+ *
+ *   d_in, d_out  device complex64 [count][L], 8-byte aligned; may not overlap.
+ *   count        >= 1.
+ *   direction    -1: X[q] = sum_n x[n] exp(-2 pi i n q / L);
+ *                +1: x[n] = sum_q X[q] exp(+2 pi i n q / L) (no 1/L).
+ * Asynchronous on hip_stream.  Errors: FDAS_EINVAL, FDAS_EHIP.
+ */
+int fdas_segment_fft(const fdas_plan *plan, const void *d_in, void *d_out, int64_t count,
+                     int32_t direction, void *hip_stream);
+
+/*
+ * fdas_plan_template_spectra -- copy the plan's pre-transformed templates
+ * H_t[q] (already scaled by 1/L) into host memory, natural order.
+ *
+ *   host_out   host complex64 [M][L].
+ * Synchronous (waits for the copy).  Errors: FDAS_EINVAL, FDAS_EHIP.
+ */
+int fdas_plan_template_spectra(const fdas_plan *plan, void *host_out);
+
+/* fdas_plan_info -- geometry and footprint of a plan (host struct, not NULL). */
+int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out);
+
+/* fdas_plan_destroy -- wait for the device, free the plan.  NULL is a no-op. */
+void fdas_plan_destroy(fdas_plan *plan);
+
+/* Static text for a status code. */
+const char *fdas_strerror(int status);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char *fdas_last_error(void);
+
+/* Name of a kernel variant id reported by fdas_plan_info. */
+const char *fdas_variant_name(int32_t variant);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDAS_H */

@@ -1,0 +1,341 @@
+// fdas_abi.cpp -- the C ABI of libfdas.so (declared in include/fdas.h):
+// argument checks, plan construction and the launches of the hot path.
+// All arithmetic of the method runs in the kernels of fdas_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fdas.h"
+#include "fdas_internal.h"
+#include "seg_fft.h"
+
+#define FDAS_API extern "C" __attribute__((visibility("default")))
+
+using fdas::c32;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? FDAS_ENOMEM : FDAS_EHIP, "%s: %s (%d)", what,
+                hipGetErrorString(e), (int)e);
+}
+
+constexpr int kVariantFusedPersistent = 1;
+
+bool supported_l(int L) { return L == 1024 || L == 2048 || L == 4096; }
+
+template <int L> int perm_of(int tau, int e) { return fdas::Seg<L>::perm(tau, e); }
+
+int perm_dispatch(int L, int tau, int e)
+{
+    switch (L) {
+    case 1024: return perm_of<1024>(tau, e);
+    case 2048: return perm_of<2048>(tau, e);
+    default: return perm_of<4096>(tau, e);
+    }
+}
+
+}  // namespace
+
+struct fdas_plan {
+    int device = 0;
+    int num_cu = 0;
+    int32_t M = 0, k_max = 0, L = 0, V = 0, kp = 0;
+    int64_t input_len = 0;
+    uint32_t flags = 0;
+    int fused_per_cu = 1;
+    c32 *d_H = nullptr;        // [M][L], permuted frequency order per template
+    c32 *d_tw = nullptr;       // [L]
+    c32 *d_taps = nullptr;     // [M][kp], zero beyond tap_len
+    int *d_tap_len = nullptr;  // [M]
+    int64_t resident_bytes = 0;
+};
+
+namespace {
+
+void free_plan(fdas_plan *p)
+{
+    if (!p) return;
+    if (p->d_H) (void)hipFree(p->d_H);
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->d_taps) (void)hipFree(p->d_taps);
+    if (p->d_tap_len) (void)hipFree(p->d_tap_len);
+    delete p;
+}
+
+int check_io(const fdas_plan *plan, const void *d_in, int64_t n, const float *d_power,
+             int64_t ld_power)
+{
+    if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    if (!d_in) return fail(FDAS_EINVAL, "d_in is NULL");
+    if (!d_power) return fail(FDAS_EINVAL, "d_power is NULL");
+    if (n < 1 || n > plan->input_len)
+        return fail(FDAS_EINVAL, "n=%lld outside [1, input_len=%lld]", (long long)n,
+                    (long long)plan->input_len);
+    if (ld_power < n) return fail(FDAS_EINVAL, "ld_power=%lld < n=%lld", (long long)ld_power, (long long)n);
+    if (((uintptr_t)d_in) % 8 != 0) return fail(FDAS_EINVAL, "d_in is not 8-byte aligned");
+    if (((uintptr_t)d_power) % 4 != 0) return fail(FDAS_EINVAL, "d_power is not 4-byte aligned");
+    return FDAS_OK;
+}
+
+}  // namespace
+
+FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *tap_len, int32_t M,
+                              int32_t K_max, int64_t input_len, int32_t seg_fft, uint32_t flags,
+                              void *hip_stream)
+{
+    g_last_error.clear();
+    if (!out) return fail(FDAS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if ((flags & ~FDAS_TAPS_ON_DEVICE) != 0)
+        return fail(FDAS_EUNSUPPORTED, "unsupported flags 0x%x (only FDAS_FP32 storage is built)", flags);
+    if (!taps) return fail(FDAS_EINVAL, "taps is NULL");
+    if (M < 1) return fail(FDAS_EINVAL, "M=%d < 1", M);
+    if (K_max < 1) return fail(FDAS_EINVAL, "K_max=%d < 1", K_max);
+    if (input_len < 1) return fail(FDAS_EINVAL, "input_len=%lld < 1", (long long)input_len);
+    const int L = seg_fft == 0 ? 2048 : seg_fft;
+    if (!supported_l(L)) return fail(FDAS_EINVAL, "seg_fft=%d not in {1024, 2048, 4096}", seg_fft);
+    if (K_max > L / 2) return fail(FDAS_EINVAL, "K_max=%d > seg_fft/2=%d", K_max, L / 2);
+    const bool on_dev = (flags & FDAS_TAPS_ON_DEVICE) != 0;
+    hipStream_t st = (hipStream_t)hip_stream;
+
+    // tap lengths, validated on the host
+    std::vector<int32_t> lens((size_t)M, K_max);
+    if (tap_len) {
+        if (on_dev) {
+            hipError_t e = hipMemcpy(lens.data(), tap_len, sizeof(int32_t) * (size_t)M, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "copying tap_len");
+        } else {
+            std::memcpy(lens.data(), tap_len, sizeof(int32_t) * (size_t)M);
+        }
+    }
+    for (int t = 0; t < M; ++t)
+        if (lens[t] < 0 || lens[t] > K_max)
+            return fail(FDAS_EINVAL, "tap_len[%d]=%d outside [0, K_max=%d]", t, lens[t], K_max);
+
+    fdas_plan *p = new (std::nothrow) fdas_plan();
+    if (!p) return fail(FDAS_ENOMEM, "host allocation of the plan failed");
+    p->M = M;
+    p->k_max = K_max;
+    p->L = L;
+    p->V = L - (K_max - 1);
+    p->kp = (K_max + 7) / 8 * 8;
+    p->input_len = input_len;
+    p->flags = flags;
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
+    e = hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+
+    const size_t bytes_H = sizeof(c32) * (size_t)M * L;
+    const size_t bytes_tw = sizeof(c32) * (size_t)L;
+    const size_t bytes_taps = sizeof(c32) * (size_t)M * p->kp;
+    const size_t bytes_len = sizeof(int) * (size_t)M;
+    p->resident_bytes = (int64_t)(bytes_H + bytes_tw + bytes_taps + bytes_len);
+    size_t free_b = 0, total_b = 0;
+    e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipMemGetInfo"); }
+    if ((size_t)p->resident_bytes > free_b) {
+        int64_t need = p->resident_bytes;
+        free_plan(p);
+        return fail(FDAS_ENOMEM, "plan needs %lld bytes, %zu free", (long long)need, free_b);
+    }
+    if ((e = hipMalloc((void **)&p->d_H, bytes_H)) != hipSuccess ||
+        (e = hipMalloc((void **)&p->d_tw, bytes_tw)) != hipSuccess ||
+        (e = hipMalloc((void **)&p->d_taps, bytes_taps)) != hipSuccess ||
+        (e = hipMalloc((void **)&p->d_tap_len, bytes_len)) != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "hipMalloc");
+    }
+
+    // taps -> [M][kp] complex64, zero beyond tap_len[t]
+    std::vector<c32> src((size_t)M * K_max);
+    if (on_dev) {
+        e = hipMemcpy(src.data(), taps, sizeof(c32) * src.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { free_plan(p); return hip_fail(e, "copying device taps"); }
+    } else {
+        std::memcpy(src.data(), taps, sizeof(c32) * src.size());
+    }
+    std::vector<c32> h((size_t)M * p->kp, fdas::mk(0.f, 0.f));
+    for (int t = 0; t < M; ++t)
+        std::memcpy(&h[(size_t)t * p->kp], &src[(size_t)t * K_max], sizeof(c32) * (size_t)lens[t]);
+    e = hipMemcpyAsync(p->d_taps, h.data(), bytes_taps, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_tap_len, lens.data(), bytes_len, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = fdas::launch_twiddles(p->d_tw, L, st);
+    if (e == hipSuccess) e = fdas::launch_tspec(p->d_taps, p->d_tap_len, p->kp, M, L, p->d_H, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "building template spectra"); }
+
+    p->fused_per_cu = fdas::fused_blocks_per_cu(L);
+    *out = p;
+    return FDAS_OK;
+}
+
+namespace {
+
+int64_t fused_grid(const fdas_plan *p, int64_t items)
+{
+    const int64_t resident = (int64_t)p->fused_per_cu * std::max(1, p->num_cu);
+    return std::max<int64_t>(1, std::min(items, resident));
+}
+
+}  // namespace
+
+FDAS_API int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
+                           int64_t ld_power, void *hip_stream)
+{
+    g_last_error.clear();
+    int rc = check_io(plan, d_in, n, d_power, ld_power);
+    if (rc != FDAS_OK) return rc;
+    fdas::FusedArgs a;
+    a.x = d_in;
+    a.n = n;
+    a.H = plan->d_H;
+    a.twL = plan->d_tw;
+    a.M = plan->M;
+    a.head = plan->k_max - 1;
+    a.V = plan->V;
+    a.L = plan->L;
+    a.items = (n + plan->V - 1) / plan->V * plan->M;
+    a.grid = fused_grid(plan, a.items);
+    a.P = d_power;
+    a.ld = ld_power;
+    hipError_t e = fdas::launch_fused(a, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the fused FDFIR kernel");
+    return FDAS_OK;
+}
+
+FDAS_API int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
+                        int64_t ld_power, void *hip_stream)
+{
+    g_last_error.clear();
+    int rc = check_io(plan, d_in, n, d_power, ld_power);
+    if (rc != FDAS_OK) return rc;
+    fdas::TdArgs a;
+    a.x = d_in;
+    a.n = n;
+    a.taps = plan->d_taps;
+    a.tap_len = plan->d_tap_len;
+    a.M = plan->M;
+    a.kp = plan->kp;
+    a.tiles = (n + fdas::TD_TILE - 1) / fdas::TD_TILE;
+    // enough workgroups to cover the chip several times over
+    const int64_t want_groups = std::max<int64_t>(1, (4LL * std::max(1, plan->num_cu) + a.tiles - 1) / a.tiles);
+    const int64_t groups = std::min<int64_t>(plan->M, want_groups);
+    a.tg = (int)((plan->M + groups - 1) / groups);
+    a.groups = (plan->M + a.tg - 1) / a.tg;
+    a.P = d_power;
+    a.ld = ld_power;
+    if (a.tiles > 0x7fffffffLL) return fail(FDAS_EINVAL, "n too large for one launch");
+    hipError_t e = fdas::launch_tdfir(a, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the TDFIR kernel");
+    return FDAS_OK;
+}
+
+FDAS_API int fdas_segment_fft(const fdas_plan *plan, const void *d_in, void *d_out, int64_t count,
+                              int32_t direction, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    if (!d_in || !d_out) return fail(FDAS_EINVAL, "NULL buffer");
+    if (count < 1 || count > 0x7fffffffLL) return fail(FDAS_EINVAL, "count=%lld out of range", (long long)count);
+    if (direction != -1 && direction != 1) return fail(FDAS_EINVAL, "direction=%d not -1 or +1", direction);
+    if (((uintptr_t)d_in) % 8 || ((uintptr_t)d_out) % 8) return fail(FDAS_EINVAL, "buffers not 8-byte aligned");
+    const char *a = (const char *)d_in, *b = (const char *)d_out;
+    const size_t bytes = sizeof(c32) * (size_t)plan->L * (size_t)count;
+    if (a < b + bytes && b < a + bytes) return fail(FDAS_EINVAL, "d_in and d_out overlap");
+    hipError_t e = fdas::launch_segfft(d_in, d_out, count, direction, plan->L, plan->d_tw,
+                                       (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the segment transform");
+    return FDAS_OK;
+}
+
+FDAS_API int fdas_plan_template_spectra(const fdas_plan *plan, void *host_out)
+{
+    g_last_error.clear();
+    if (!plan || !host_out) return fail(FDAS_EINVAL, "NULL argument");
+    const int L = plan->L, T = L / 16;
+    std::vector<c32> tmp((size_t)plan->M * L);
+    hipError_t e = hipMemcpy(tmp.data(), plan->d_H, sizeof(c32) * tmp.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copying template spectra");
+    c32 *dst = (c32 *)host_out;
+    for (int t = 0; t < plan->M; ++t)
+        for (int e16 = 0; e16 < 16; ++e16)
+            for (int tau = 0; tau < T; ++tau)
+                dst[(size_t)t * L + perm_dispatch(L, tau, e16)] = tmp[(size_t)t * L + (size_t)e16 * T + tau];
+    return FDAS_OK;
+}
+
+FDAS_API int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out)
+{
+    g_last_error.clear();
+    if (!plan || !out) return fail(FDAS_EINVAL, "NULL argument");
+    std::memset(out, 0, sizeof *out);
+    out->seg_fft = plan->L;
+    out->valid_per_seg = plan->V;
+    out->num_segments = (plan->input_len + plan->V - 1) / plan->V;
+    out->k_max = plan->k_max;
+    out->num_templates = plan->M;
+    out->input_len = plan->input_len;
+    out->resident_bytes = plan->resident_bytes;
+    out->threads_per_fft = plan->L / 16;
+    out->fused_grid = (int32_t)fused_grid(plan, out->num_segments * plan->M);
+    out->variant = kVariantFusedPersistent;
+    out->device = plan->device;
+    return FDAS_OK;
+}
+
+FDAS_API void fdas_plan_destroy(fdas_plan *plan)
+{
+    if (!plan) return;
+    const int dev = plan->device;
+    int cur = dev;
+    if (hipGetDevice(&cur) == hipSuccess && cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    if (cur != dev) (void)hipSetDevice(cur);
+}
+
+FDAS_API const char *fdas_strerror(int status)
+{
+    switch (status) {
+    case FDAS_OK: return "ok";
+    case FDAS_EINVAL: return "invalid argument";
+    case FDAS_ENOMEM: return "out of device memory";
+    case FDAS_EHIP: return "HIP runtime error";
+    case FDAS_EUNSUPPORTED: return "unsupported flag or precision";
+    default: return "unknown status";
+    }
+}
+
+FDAS_API const char *fdas_last_error(void) { return g_last_error.c_str(); }
+
+FDAS_API const char *fdas_variant_name(int32_t variant)
+{
+    switch (variant) {
+    case kVariantFusedPersistent: return "fused-ols-persistent-fp32";
+    default: return "unknown";
+    }
+}

@@ -1,0 +1,48 @@
+// fdas_internal.h -- interface between the C ABI (fdas_abi.cpp) and the
+// kernel launchers (fdas_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdas {
+
+struct c32;
+
+constexpr int TD_THREADS = 256;              // work-items per TDFIR workgroup
+constexpr int TD_R = 8;                      // consecutive outputs per work-item
+constexpr int TD_TILE = TD_THREADS * TD_R;   // outputs per TDFIR workgroup
+
+struct FusedArgs {
+    const void *x;        // complex64 [n]
+    int64_t n;
+    const void *H;        // complex64 [M][L], permuted order
+    const c32 *twL;       // complex64 [L]
+    int M, head, V, L;
+    int64_t items;        // S * M
+    int64_t grid;         // workgroups
+    float *P;
+    int64_t ld;
+};
+
+struct TdArgs {
+    const void *x;
+    int64_t n;
+    const void *taps;     // complex64 [M][kp]
+    const int *tap_len;
+    int M, kp, tg;
+    int64_t tiles, groups;
+    float *P;
+    int64_t ld;
+};
+
+hipError_t launch_twiddles(c32 *twL, int L, hipStream_t st);
+hipError_t launch_tspec(const c32 *taps, const int *tap_len, int kp, int M, int L, c32 *H,
+                        hipStream_t st);
+int fused_blocks_per_cu(int L);
+hipError_t launch_fused(const FusedArgs &a, hipStream_t st);
+hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int L, const c32 *twL,
+                         hipStream_t st);
+size_t tdfir_lds_bytes(int kp);
+hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
+
+}  // namespace fdas

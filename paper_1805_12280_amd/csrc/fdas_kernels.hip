@@ -1,0 +1,327 @@
+// fdas_kernels.hip -- gfx950 kernels of the FT-convolution hot path and
+// their launchers (host side, C++ linkage, used by fdas_abi.cpp only).
+//
+//   twiddle_kernel     W_L^e = exp(-2 pi i e / L), float64 -> complex64 table
+//   tspec_kernel       pre-transformed templates (Alg. 2, FFT of h once), in
+//                      float64 from the complex64 taps, 1/L folded in, stored
+//                      in the segment transform's permuted frequency order
+//   fdfir_fused_kernel the overlap-save hot path (Section 3.2.2, Alg. 2):
+//                      segment gather with a K_max-1 halo, one forward FFT
+//                      per segment shared by all templates (the AOLS
+//                      amortisation, Section 4.2.1), pointwise product,
+//                      inverse FFT, discard of the first K_max-1 points and
+//                      |y|^2 (Section 4.3), all in one persistent launch
+//   segfft_kernel      the segment transform alone, natural order in/out
+//   tdfir_kernel       direct Eq. (1) with taps in blocks of 8 accumulated in
+//                      registers (overlap-add on the taps, Alg. 1)
+#include "fdas_internal.h"
+#include "seg_fft.h"
+
+namespace fdas {
+
+// ---------------------------------------------------------------------------
+// plan-time tables (float64 arithmetic, rounded once)
+// ---------------------------------------------------------------------------
+
+__global__ void twiddle_kernel(c32 *twL, int L)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= L) return;
+    double s, c;
+    sincospi(-2.0 * (double)e / (double)L, &s, &c);
+    twL[e] = mk((float)c, (float)s);
+}
+
+template <int L>
+__global__ void tspec_kernel(const c32 *__restrict__ taps, const int *__restrict__ tap_len,
+                             int kp, int M, c32 *__restrict__ H)
+{
+    using SG = Seg<L>;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * L) return;
+    const int t = (int)(idx / L);
+    const int rem = (int)(idx - (int64_t)t * L);
+    const int e = rem / SG::T, tau = rem - e * SG::T;
+    const int q = SG::perm(tau, e);
+    const c32 *h = taps + (int64_t)t * kp;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < tap_len[t]; ++k) {
+        const int r = (int)(((int64_t)q * k) & (L - 1));     // exact phase reduction
+        double s, c;
+        sincospi(-2.0 * (double)r / (double)L, &s, &c);
+        const double hr = h[k].re, hi = h[k].im;
+        re += hr * c - hi * s;
+        im += hr * s + hi * c;
+    }
+    H[(int64_t)t * L + rem] = mk((float)(re / L), (float)(im / L));
+}
+
+// ---------------------------------------------------------------------------
+// fused overlap-save FDFIR + power
+// ---------------------------------------------------------------------------
+
+// Work item u in [0, S*M) is (segment s = u / M, template t = u % M).  Each
+// workgroup takes one contiguous range of items, so it transforms a segment
+// forward once and reuses the spectrum for every template of that segment
+// in its range.
+template <int L>
+__global__ __launch_bounds__(L / 16) void fdfir_fused_kernel(
+    const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ H, const c32 *__restrict__ twL,
+    int M, int head, int V, int64_t items, float *__restrict__ P, int64_t ld)
+{
+    using SG = Seg<L>;
+    constexpr int T = SG::T;
+    __shared__ c32 lds[SG::LDS_ELEMS];
+    const int tau = threadIdx.x;
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
+    if (u0 >= u1) return;
+
+    c32 tw1[16], tw2[16];
+    SG::inv_twiddles(tau, twL, tw1, tw2);
+
+    c32 X[16];
+    int64_t cur = -1;
+    for (int64_t u = u0; u < u1; ++u) {
+        const int64_t s = u / M;
+        const int t = (int)(u - s * M);
+        // input index of segment point j is base + j; it is also the output
+        // index of point j, which is kept when j >= head = K_max - 1
+        const int64_t base = s * V - head;
+        if (s != cur) {
+            cur = s;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int64_t i = base + tau + T * m;
+                X[m] = (i >= 0 && i < n) ? x[i] : mk(0.f, 0.f);
+            }
+            SG::fwd0(tau, X, twL);
+            __syncthreads();
+            SG::put_a(tau, X, lds);
+            __syncthreads();
+            SG::fwd1(tau, X, lds, twL);
+            __syncthreads();
+            SG::put_c(tau, X, lds);
+            __syncthreads();
+            SG::fwd2(tau, X, lds);
+        }
+        c32 v[16];
+        const c32 *Ht = H + (int64_t)t * L + tau;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = mul(X[e], Ht[e * T]);
+        __syncthreads();
+        SG::inv2(tau, v, lds, tw2);
+        __syncthreads();
+        SG::inv1(tau, v, lds, tw1);
+        __syncthreads();
+        SG::put_a_inv(tau, v, lds);
+        __syncthreads();
+        SG::inv0(tau, v, lds);
+        float *Pt = P + (int64_t)t * ld;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = tau + T * m;
+            const int64_t o = base + j;
+            if (j >= head && o < n) __builtin_nontemporal_store(norm2(v[m]), Pt + o);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone segment transform (natural order in and out)
+// ---------------------------------------------------------------------------
+
+template <int L, int DIR>
+__global__ __launch_bounds__(L / 16) void segfft_kernel(const c32 *__restrict__ in,
+                                                        c32 *__restrict__ out,
+                                                        const c32 *__restrict__ twL)
+{
+    using SG = Seg<L>;
+    constexpr int T = SG::T;
+    __shared__ c32 lds[SG::LDS_ELEMS];
+    const int tau = threadIdx.x;
+    const c32 *src = in + (int64_t)blockIdx.x * L;
+    c32 *dst = out + (int64_t)blockIdx.x * L;
+    c32 v[16];
+    if (DIR < 0) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = src[tau + T * m];
+        SG::fwd0(tau, v, twL);
+        SG::put_a(tau, v, lds);
+        __syncthreads();
+        SG::fwd1(tau, v, lds, twL);
+        __syncthreads();
+        SG::put_c(tau, v, lds);
+        __syncthreads();
+        SG::fwd2(tau, v, lds);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dst[SG::perm(tau, e)] = v[e];
+    } else {
+        c32 tw1[16], tw2[16];
+        SG::inv_twiddles(tau, twL, tw1, tw2);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = src[SG::perm(tau, e)];
+        SG::inv2(tau, v, lds, tw2);
+        __syncthreads();
+        SG::inv1(tau, v, lds, tw1);
+        __syncthreads();
+        SG::put_a_inv(tau, v, lds);
+        __syncthreads();
+        SG::inv0(tau, v, lds);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) dst[tau + T * m] = v[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct TDFIR baseline
+// ---------------------------------------------------------------------------
+
+// Tile of TD_TILE outputs per workgroup, TD_R consecutive outputs per
+// work-item.  LDS holds x[i0 - kp .. i0 + TD_TILE) with one pad slot every 8
+// elements, so work-items 8 elements apart hit different banks.
+__device__ __forceinline__ int td_skew(int e) { return e + (e >> 3); }
+
+__global__ __launch_bounds__(TD_THREADS) void tdfir_kernel(
+    const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ taps,
+    const int *__restrict__ tap_len, int M, int kp, int tg, float *__restrict__ P, int64_t ld)
+{
+    extern __shared__ c32 xs[];
+    const int tau = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * TD_TILE;
+    const int64_t org = i0 - kp;
+    const int span = TD_TILE + kp;
+    for (int l = tau; l < span; l += TD_THREADS) {
+        const int64_t i = org + l;
+        xs[td_skew(l)] = (i >= 0 && i < n) ? x[i] : mk(0.f, 0.f);
+    }
+    __syncthreads();
+    const int t_end = min(M, (int)(blockIdx.y + 1) * tg);
+    for (int t = blockIdx.y * tg; t < t_end; ++t) {
+        const c32 *h = taps + (int64_t)t * kp;
+        const int nblk = (tap_len[t] + 7) >> 3;
+        c32 acc[TD_R];
+#pragma unroll
+        for (int r = 0; r < TD_R; ++r) acc[r] = mk(0.f, 0.f);
+        // one block of 8 taps: y[i] += sum_{k in block} x[i-k] h[k]
+        for (int blk = 0; blk < nblk; ++blk) {
+            const int kb = blk * 8;
+            c32 win[15];
+            const int l0 = TD_R * tau + kp - kb - 7;
+#pragma unroll
+            for (int c = 0; c < 15; ++c) win[c] = xs[td_skew(l0 + c)];
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const c32 hk = h[kb + kk];
+#pragma unroll
+                for (int r = 0; r < TD_R; ++r) {
+                    const c32 xv = win[r - kk + 7];
+                    acc[r].re = fmaf(xv.re, hk.re, acc[r].re);
+                    acc[r].re = fmaf(-xv.im, hk.im, acc[r].re);
+                    acc[r].im = fmaf(xv.re, hk.im, acc[r].im);
+                    acc[r].im = fmaf(xv.im, hk.re, acc[r].im);
+                }
+            }
+        }
+        float *Pt = P + (int64_t)t * ld;
+        const int64_t ib = i0 + TD_R * tau;
+#pragma unroll
+        for (int r = 0; r < TD_R; ++r)
+            if (ib + r < n) __builtin_nontemporal_store(norm2(acc[r]), Pt + ib + r);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_twiddles(c32 *twL, int L, hipStream_t st)
+{
+    hipLaunchKernelGGL(twiddle_kernel, dim3((L + 255) / 256), dim3(256), 0, st, twL, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_tspec(const c32 *taps, const int *tap_len, int kp, int M, int L, c32 *H,
+                        hipStream_t st)
+{
+    const int64_t total = (int64_t)M * L;
+    dim3 grid((unsigned)((total + 255) / 256)), blk(256);
+    switch (L) {
+    case 1024: hipLaunchKernelGGL(tspec_kernel<1024>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
+    case 2048: hipLaunchKernelGGL(tspec_kernel<2048>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
+    case 4096: hipLaunchKernelGGL(tspec_kernel<4096>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int fused_blocks_per_cu(int L)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (L) {
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<1024>, 1024 / 16, 0); break;
+    case 2048: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<2048>, 2048 / 16, 0); break;
+    case 4096: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<4096>, 4096 / 16, 0); break;
+    default: break;
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_fused(const FusedArgs &a, hipStream_t st)
+{
+    dim3 grid((unsigned)a.grid), blk(a.L / 16);
+    switch (a.L) {
+    case 1024:
+        hipLaunchKernelGGL(fdfir_fused_kernel<1024>, grid, blk, 0, st, (const c32 *)a.x, a.n,
+                           (const c32 *)a.H, (const c32 *)a.twL, a.M, a.head, a.V, a.items, a.P, a.ld);
+        break;
+    case 2048:
+        hipLaunchKernelGGL(fdfir_fused_kernel<2048>, grid, blk, 0, st, (const c32 *)a.x, a.n,
+                           (const c32 *)a.H, (const c32 *)a.twL, a.M, a.head, a.V, a.items, a.P, a.ld);
+        break;
+    case 4096:
+        hipLaunchKernelGGL(fdfir_fused_kernel<4096>, grid, blk, 0, st, (const c32 *)a.x, a.n,
+                           (const c32 *)a.H, (const c32 *)a.twL, a.M, a.head, a.V, a.items, a.P, a.ld);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int L, const c32 *twL,
+                         hipStream_t st)
+{
+    dim3 grid((unsigned)count), blk(L / 16);
+    const c32 *i = (const c32 *)in;
+    c32 *o = (c32 *)out;
+#define FDAS_SEGFFT_CASE(LL)                                                                   \
+    case LL:                                                                                    \
+        if (dir < 0) hipLaunchKernelGGL((segfft_kernel<LL, -1>), grid, blk, 0, st, i, o, twL);  \
+        else hipLaunchKernelGGL((segfft_kernel<LL, 1>), grid, blk, 0, st, i, o, twL);           \
+        break;
+    switch (L) {
+        FDAS_SEGFFT_CASE(1024)
+        FDAS_SEGFFT_CASE(2048)
+        FDAS_SEGFFT_CASE(4096)
+    default: return hipErrorInvalidValue;
+    }
+#undef FDAS_SEGFFT_CASE
+    return hipGetLastError();
+}
+
+size_t tdfir_lds_bytes(int kp)
+{
+    const int span = TD_TILE + kp;
+    return sizeof(c32) * (size_t)(span + span / 8 + 2);
+}
+
+hipError_t launch_tdfir(const TdArgs &a, hipStream_t st)
+{
+    dim3 grid((unsigned)a.tiles, (unsigned)a.groups), blk(TD_THREADS);
+    hipLaunchKernelGGL(tdfir_kernel, grid, blk, tdfir_lds_bytes(a.kp), st, (const c32 *)a.x, a.n,
+                       (const c32 *)a.taps, a.tap_len, a.M, a.kp, a.tg, a.P, a.ld);
+    return hipGetLastError();
+}
+
+}  // namespace fdas

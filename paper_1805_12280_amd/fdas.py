@@ -1,0 +1,228 @@
+"""ctypes binding of libfdas.so (include/fdas.h): argument marshalling only.
+
+Every step of the FT convolution runs in the library's HIP kernels; torch is
+used here for device memory and the current stream.  Loading fails loudly
+when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfdas.so")
+
+FDAS_OK, FDAS_EINVAL, FDAS_ENOMEM, FDAS_EHIP, FDAS_EUNSUPPORTED = 0, 1, 2, 3, 4
+FDAS_FP32 = 0
+FDAS_TAPS_ON_DEVICE = 1
+
+EXPORTED = ("fdas_plan_create", "fdas_convolve", "fdas_tdfir", "fdas_segment_fft",
+            "fdas_plan_template_spectra", "fdas_plan_info", "fdas_plan_destroy",
+            "fdas_strerror", "fdas_last_error", "fdas_variant_name")
+
+
+class FdasError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fdas error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("seg_fft", ctypes.c_int32), ("valid_per_seg", ctypes.c_int32),
+                ("num_segments", ctypes.c_int64), ("k_max", ctypes.c_int32),
+                ("num_templates", ctypes.c_int32), ("input_len", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_int64), ("threads_per_fft", ctypes.c_int32),
+                ("fused_grid", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfdas.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if not os.path.exists(path):
+        raise FdasError(FDAS_EHIP, f"{path} is not built; run __graft_entry__.build()")
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.fdas_plan_create.argtypes = [ctypes.POINTER(vp), vp, vp, i32, i32, i64, i32, ctypes.c_uint32, vp]
+    lib.fdas_plan_create.restype = ctypes.c_int
+    for name in ("fdas_convolve", "fdas_tdfir"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, i64, vp, i64, vp]
+        f.restype = ctypes.c_int
+    lib.fdas_segment_fft.argtypes = [vp, vp, vp, i64, i32, vp]
+    lib.fdas_segment_fft.restype = ctypes.c_int
+    lib.fdas_plan_template_spectra.argtypes = [vp, vp]
+    lib.fdas_plan_template_spectra.restype = ctypes.c_int
+    lib.fdas_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.fdas_plan_info.restype = ctypes.c_int
+    lib.fdas_plan_destroy.argtypes = [vp]
+    lib.fdas_plan_destroy.restype = None
+    lib.fdas_strerror.argtypes = [ctypes.c_int]
+    lib.fdas_strerror.restype = ctypes.c_char_p
+    lib.fdas_last_error.argtypes = []
+    lib.fdas_last_error.restype = ctypes.c_char_p
+    lib.fdas_variant_name.argtypes = [i32]
+    lib.fdas_variant_name.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def check(rc: int):
+    if rc != FDAS_OK:
+        lib = load_library()
+        raise FdasError(rc, f"{lib.fdas_strerror(rc).decode()}: {lib.fdas_last_error().decode()}")
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A template bank resident on the GPU, ready to filter spectra.
+
+    taps:     complex64 [M, K_max] (numpy, CPU or CUDA torch), zero beyond tap_len
+    tap_len:  int32 [M] or None (all K_max)
+    input_len: largest spectrum length that will be filtered
+    seg_fft:  segment transform length L in {1024, 2048, 4096}
+    """
+
+    def __init__(self, taps, tap_len=None, input_len: int = 1 << 22, seg_fft: int = 2048,
+                 precision: str = "fp32", stream=None):
+        import torch
+        if precision != "fp32":
+            raise FdasError(FDAS_EUNSUPPORTED, f"precision {precision!r} is not built")
+        lib = load_library()
+        flags = FDAS_FP32
+        keep = []
+        if isinstance(taps, torch.Tensor) and taps.is_cuda:
+            taps_t = taps.to(torch.complex64).contiguous()
+            keep.append(taps_t)
+            taps_p = _ptr(taps_t)
+            flags |= FDAS_TAPS_ON_DEVICE
+            m, k_max = taps_t.shape
+            if tap_len is not None:
+                tl = torch.as_tensor(tap_len, dtype=torch.int32, device=taps_t.device).contiguous()
+                keep.append(tl)
+                len_p = _ptr(tl)
+            else:
+                len_p = None
+        else:
+            if isinstance(taps, torch.Tensor):
+                taps = taps.numpy()
+            taps_np = np.ascontiguousarray(np.asarray(taps, dtype=np.complex64))
+            if taps_np.ndim != 2:
+                raise FdasError(FDAS_EINVAL, "taps must be [M, K_max]")
+            keep.append(taps_np)
+            taps_p = ctypes.c_void_p(taps_np.ctypes.data)
+            m, k_max = taps_np.shape
+            if tap_len is not None:
+                tl = np.ascontiguousarray(np.asarray(tap_len, dtype=np.int32))
+                if tl.shape != (m,):
+                    raise FdasError(FDAS_EINVAL, "tap_len must be [M]")
+                keep.append(tl)
+                len_p = ctypes.c_void_p(tl.ctypes.data)
+            else:
+                len_p = None
+        handle = ctypes.c_void_p()
+        check(lib.fdas_plan_create(ctypes.byref(handle), taps_p, len_p, int(m), int(k_max),
+                                   int(input_len), int(seg_fft), flags, _stream_handle(stream)))
+        self._h = handle
+        self._lib = lib
+        self.num_templates = int(m)
+        self.k_max = int(k_max)
+        self.input_len = int(input_len)
+        info = self.info
+        self.seg_fft = info.seg_fft
+        self.device = info.device
+
+    # -- properties ---------------------------------------------------------
+    @property
+    def info(self) -> PlanInfo:
+        out = PlanInfo()
+        check(self._lib.fdas_plan_info(self._h, ctypes.byref(out)))
+        return out
+
+    @property
+    def variant(self) -> str:
+        return self._lib.fdas_variant_name(self.info.variant).decode()
+
+    # -- calls --------------------------------------------------------------
+    def _io(self, x, out):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64):
+            raise FdasError(FDAS_EINVAL, "x must be a CUDA complex64 tensor")
+        if x.dim() != 1 or not x.is_contiguous():
+            raise FdasError(FDAS_EINVAL, "x must be 1-D and contiguous")
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((self.num_templates, n), dtype=torch.float32, device=x.device)
+        if out.dtype != torch.float32 or not out.is_cuda or out.dim() != 2 or out.stride(1) != 1 \
+                or out.shape[0] != self.num_templates or out.shape[1] < n:
+            raise FdasError(FDAS_EINVAL, "out must be CUDA float32 [M, >=n] with unit column stride")
+        return n, out
+
+    def convolve(self, x, out=None, stream=None):
+        """Power plane P[t, i] = |sum_k x[i-k] h_t[k]|^2 via overlap-save FDFIR."""
+        n, out = self._io(x, out)
+        check(self._lib.fdas_convolve(self._h, _ptr(x), n, _ptr(out), out.stride(0),
+                                      _stream_handle(stream)))
+        return out
+
+    def tdfir(self, x, out=None, stream=None):
+        """The same power plane by direct time-domain FIR."""
+        n, out = self._io(x, out)
+        check(self._lib.fdas_tdfir(self._h, _ptr(x), n, _ptr(out), out.stride(0),
+                                   _stream_handle(stream)))
+        return out
+
+    def segment_fft(self, x, direction: int = -1, stream=None):
+        """The plan's L-point transform on each row of x [count, L] (natural order)."""
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64
+                and x.dim() == 2 and x.shape[1] == self.seg_fft and x.is_contiguous()):
+            raise FdasError(FDAS_EINVAL, "x must be CUDA complex64 [count, L], contiguous")
+        out = torch.empty_like(x)
+        check(self._lib.fdas_segment_fft(self._h, _ptr(x), _ptr(out), x.shape[0], int(direction),
+                                         _stream_handle(stream)))
+        return out
+
+    def template_spectra(self) -> np.ndarray:
+        """H_t[q] (1/L folded in), complex64 [M, L], natural order, on the host."""
+        out = np.empty((self.num_templates, self.seg_fft), dtype=np.complex64)
+        check(self._lib.fdas_plan_template_spectra(self._h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fdas_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,104 @@
+"""Comparison helpers shared by the GPU parity tests, smoke() and the bench:
+the acceptance metric (max error normalised to the peak oracle power), the
+paper's rRMSE, and the tie-aware top-k rule."""
+from __future__ import annotations
+
+import heapq
+
+import numpy as np
+
+FP32_TOL = 1e-4      # max |P_gpu - P_ref| / max P_ref for the float32 path
+TOPK = 16
+
+
+class PlaneStats:
+    """Streams row blocks of (gpu, oracle) power and accumulates the metrics."""
+
+    def __init__(self, k: int = TOPK):
+        self.k = k
+        self.max_abs = 0.0
+        self.max_ref = 0.0
+        self.sq_err = 0.0
+        self.sq_ref = 0.0
+        self.gpu_heap = []    # min-heap of (P, -t, -i) keeping the k largest
+        self.ref_heap = []
+        self.gpu_vals = {}    # (t, i) -> gpu power of candidates
+        self.ref_rows = {}    # (t, i) -> oracle power of candidates
+
+    def _push(self, heap, vals, rows_t, block):
+        k = self.k
+        flat = block.reshape(-1)
+        if flat.size == 0:
+            return
+        take = min(k, flat.size)
+        idx = np.argpartition(flat, flat.size - take)[flat.size - take:]
+        # include every cell tied with the smallest kept value
+        thr = flat[idx].min()
+        idx = np.nonzero(flat >= thr)[0]
+        n = block.shape[1]
+        for c in idx.tolist():
+            t, i = rows_t[c // n], c % n
+            item = (float(flat[c]), -int(t), -int(i))
+            if len(heap) < k:
+                heapq.heappush(heap, item)
+            elif item > heap[0]:
+                heapq.heapreplace(heap, item)
+
+    def add(self, rows_t, gpu_block, ref_block):
+        gpu_block = np.asarray(gpu_block, dtype=np.float64)
+        ref_block = np.asarray(ref_block, dtype=np.float64)
+        d = np.abs(gpu_block - ref_block)
+        self.max_abs = max(self.max_abs, float(d.max()) if d.size else 0.0)
+        self.max_ref = max(self.max_ref, float(ref_block.max()) if ref_block.size else 0.0)
+        self.sq_err += float(np.sum(d * d))
+        self.sq_ref += float(np.sum(ref_block * ref_block))
+        rows_t = list(rows_t)
+        self._push(self.gpu_heap, None, rows_t, gpu_block)
+        self._push(self.ref_heap, None, rows_t, ref_block)
+        # remember both powers of every cell that is (or was) a candidate on either side
+        n = gpu_block.shape[1]
+        for heap in (self.gpu_heap, self.ref_heap):
+            for _, mt, mi in heap:
+                t, i = -mt, -mi
+                if t in rows_t:
+                    r = rows_t.index(t)
+                    self.gpu_vals[(t, i)] = float(gpu_block[r, i])
+                    self.ref_rows[(t, i)] = float(ref_block[r, i])
+        del n
+
+    @property
+    def norm_err(self) -> float:
+        return self.max_abs / self.max_ref if self.max_ref > 0 else self.max_abs
+
+    @property
+    def rrmse(self) -> float:
+        return float(np.sqrt(self.sq_err / self.sq_ref)) if self.sq_ref > 0 else 0.0
+
+    def topk(self, which: str):
+        heap = self.gpu_heap if which == "gpu" else self.ref_heap
+        return [(-mt, -mi, p) for p, mt, mi in sorted(heap, reverse=True)]
+
+    def topk_agree(self, tol: float = FP32_TOL):
+        """Top-k sets equal, except cells whose oracle power lies within
+        tol * max(P_ref) of the oracle's k-th value may swap."""
+        ref = self.topk("ref")
+        gpu = self.topk("gpu")
+        if not ref:
+            return True, []
+        kth = ref[-1][2]
+        slack = tol * self.max_ref
+        ref_set = {(t, i) for t, i, _ in ref}
+        gpu_set = {(t, i) for t, i, _ in gpu}
+        bad = []
+        for c in gpu_set - ref_set:
+            if c not in self.ref_rows or self.ref_rows[c] < kth - slack:
+                bad.append(("extra", c, self.ref_rows.get(c)))
+        for c in ref_set - gpu_set:
+            if self.ref_rows[c] > kth + slack:
+                bad.append(("missing", c, self.ref_rows[c]))
+        return not bad, bad
+
+    def summary(self) -> dict:
+        ok, bad = self.topk_agree()
+        return {"norm_err": self.norm_err, "rrmse": self.rrmse, "max_ref": self.max_ref,
+                "topk_ok": ok, "topk_mismatch": bad[:4]}

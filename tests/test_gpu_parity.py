@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (float32 path): max |P_gpu - P_ref| / max P_ref <= 1e-4 per input array,
+and the same top-16 (template, bin) cells up to the near-tie rule."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from fdas_check import FP32_TOL, PlaneStats
+from paper_1805_12280_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def fdas(torch_cuda):
+    import os
+    from paper_1805_12280_amd import fdas as f
+    if not os.path.exists(f.LIB_PATH):
+        from paper_1805_12280_amd import build
+        build.build()
+    f.load_library()
+    return f
+
+
+def run_plane(torch, plan, x_np, method, n=None, ld=None):
+    n = x_np.shape[0] if n is None else n
+    x = torch.from_numpy(np.ascontiguousarray(x_np[:n])).cuda()
+    ld = n if ld is None else ld
+    out = torch.full((plan.num_templates, ld), -7.0, dtype=torch.float32, device="cuda")
+    getattr(plan, method)(x, out=out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def compare(P, x_np, bank, n, rows_per_block=16, threads=0):
+    st = PlaneStats()
+    m = bank.num_templates
+    for r0 in range(0, m, rows_per_block):
+        rows = list(range(r0, min(m, r0 + rows_per_block)))
+        ref = oracle.power(x_np[:n], bank.taps, bank.tap_len, rows=rows, nthreads=threads)
+        st.add(rows, P[rows, :n], ref)
+    return st
+
+
+@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("method", ["convolve", "tdfir"])
+def test_toy_full_plane(torch_cuda, fdas, toy, L, method):
+    _say(f"[toy] 9 x 2^16 L={L} {method}")
+    plan = fdas.Plan(toy.bank.taps, toy.bank.tap_len, input_len=toy.n, seg_fft=L)
+    P = run_plane(torch_cuda, plan, toy.x, method)
+    st = compare(P, toy.x, toy.bank, toy.n)
+    _say(st.summary())
+    assert st.norm_err <= FP32_TOL
+    ok, bad = st.topk_agree()
+    assert ok, bad
+    # the chirp (z0 = +6) is de-chirped by the template of drift -6
+    t_best, i_best, _ = st.topk("gpu")[0]
+    assert toy.bank.z[t_best] == -6
+
+
+def test_ska_headline_full_plane(torch_cuda, fdas):
+    """85 templates x 2^22 points, L = 2048: the launch the bench times,
+    compared with the oracle over the whole plane."""
+    w = datagen.ska_workload()
+    _say(f"[ska] {w.name} L={w.seg_fft} convolve, full-plane oracle")
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=w.n, seg_fft=w.seg_fft)
+    x = torch_cuda.from_numpy(w.x).cuda()
+    out = torch_cuda.empty((85, w.n), dtype=torch_cuda.float32, device="cuda")
+    plan.convolve(x, out=out)
+    torch_cuda.cuda.synchronize()
+    st = PlaneStats()
+    for r0 in range(0, 85, 17):
+        rows = list(range(r0, r0 + 17))
+        gpu = out[r0:r0 + 17].cpu().numpy()
+        ref = oracle.power(w.x, w.bank.taps, w.bank.tap_len, rows=rows)
+        st.add(rows, gpu, ref)
+        _say(f"  rows {r0}..{r0 + 16}: norm_err so far {st.norm_err:.3e}")
+    _say(st.summary())
+    assert st.norm_err <= FP32_TOL
+    ok, bad = st.topk_agree()
+    assert ok, bad
+    # every injected chirp shows up among the candidates, de-chirped by the
+    # template of opposite drift
+    top = st.topk("gpu")
+    for c in w.chirps:
+        assert any(abs(i - c.r0) < 300 and abs(w.bank.z[t] + c.z0) <= 1.5 for t, i, _ in top), c
+
+
+@pytest.mark.parametrize("L", [1024, 4096])
+def test_ska_other_segment_lengths_rows(torch_cuda, fdas, L):
+    """Headline input at the other segment lengths: every row, compared on the
+    full length for a subset of templates (short, medium and longest)."""
+    w = datagen.ska_workload()
+    _say(f"[ska] L={L} rows 0,21,42,63,84")
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=w.n, seg_fft=L)
+    x = torch_cuda.from_numpy(w.x).cuda()
+    out = plan.convolve(x)
+    rows = [0, 21, 42, 63, 84]
+    gpu = out[rows].cpu().numpy()
+    ref = oracle.power(w.x, w.bank.taps, w.bank.tap_len, rows=rows)
+    st = PlaneStats()
+    st.add(rows, gpu, ref)
+    _say(st.summary())
+    assert st.norm_err <= FP32_TOL
+
+
+@pytest.mark.parametrize("seed,n,m,k_max,L", [
+    (1, 1, 3, 17, 1024),          # a single output
+    (2, 924, 2, 101, 1024),       # n = V exactly
+    (3, 923, 2, 101, 1024),       # n = V - 1
+    (4, 925, 2, 101, 1024),       # n = V + 1
+    (5, 5000, 5, 1, 2048),        # one tap: P = |h0|^2 |x|^2
+    (6, 9001, 3, 1024, 2048),     # K_max = L / 2
+    (7, 20011, 1, 64, 4096),      # M = 1, prime length
+    (8, 70001, 7, 77, 2048),      # ragged taps, several segments, ragged tail
+])
+@pytest.mark.parametrize("method", ["convolve", "tdfir"])
+def test_edge_cases(torch_cuda, fdas, seed, n, m, k_max, L, method):
+    _say(f"[edge] seed={seed} n={n} m={m} k_max={k_max} L={L} {method}")
+    x, bank = datagen.random_case(seed, n, m, k_max)
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n + 17, seg_fft=L)
+    P = run_plane(torch_cuda, plan, x, method, ld=n + 5)
+    assert np.all(P[:, n:] == -7.0), "wrote past n"
+    st = compare(P, x, bank, n)
+    assert st.norm_err <= FP32_TOL, st.summary()
+
+
+def test_prefix_length_and_zero_template(torch_cuda, fdas):
+    """n < input_len, and a template with zero taps gives an all-zero row."""
+    x, bank = datagen.random_case(9, 30000, 4, 40)
+    tl = bank.tap_len.copy()
+    tl[2] = 0
+    plan = fdas.Plan(bank.taps, tl, input_len=30000, seg_fft=1024)
+    for n in (12345, 30000):
+        for method in ("convolve", "tdfir"):
+            P = run_plane(torch_cuda, plan, x, method, n=n)
+            assert np.all(P[2] == 0.0)
+            st = compare(P, x, datagen.Bank(bank.z, bank.taps, tl), n)
+            assert st.norm_err <= FP32_TOL
+
+
+def test_impulse_gives_template_power(torch_cuda, fdas):
+    _, bank = datagen.random_case(10, 8, 3, 50)
+    n, j0 = 5000, 1777
+    x = np.zeros(n, np.complex64)
+    x[j0] = 1.0
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n, seg_fft=1024)
+    for method in ("convolve", "tdfir"):
+        P = run_plane(torch_cuda, plan, x, method)
+        for t in range(3):
+            kt = int(bank.tap_len[t])
+            ref = np.zeros(n)
+            ref[j0:j0 + kt] = np.abs(bank.taps[t, :kt].astype(np.complex128)) ** 2
+            assert np.max(np.abs(P[t] - ref)) <= FP32_TOL * ref.max()
+
+
+def test_deterministic_and_two_streams(torch_cuda, fdas, toy):
+    torch = torch_cuda
+    plan = fdas.Plan(toy.bank.taps, toy.bank.tap_len, input_len=toy.n, seg_fft=1024)
+    x = torch.from_numpy(toy.x).cuda()
+    a = plan.convolve(x)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        b = plan.convolve(x)
+    with torch.cuda.stream(s2):
+        c = plan.convolve(x)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_taps_on_device(torch_cuda, fdas, toy):
+    torch = torch_cuda
+    p_host = fdas.Plan(toy.bank.taps, toy.bank.tap_len, input_len=toy.n, seg_fft=2048)
+    p_dev = fdas.Plan(torch.from_numpy(toy.bank.taps).cuda(), toy.bank.tap_len,
+                      input_len=toy.n, seg_fft=2048)
+    x = torch.from_numpy(toy.x).cuda()
+    assert torch.equal(p_host.convolve(x), p_dev.convolve(x))
+    assert np.array_equal(p_host.template_spectra(), p_dev.template_spectra())
