@@ -61,8 +61,9 @@ def algorithmic_bytes(n, m, L):
     return 8 * n + 4 * m * n + 8 * m * L
 
 
-def nominal_flops(n, m, L, k_max):
-    v = L - (k_max - 1)
+def nominal_flops(n, m, L, v):
+    """5 L log2 L per transform (the paper's C = 5), 6 per complex product,
+    3 per power value; one forward transform per segment."""
     s = math.ceil(n / v)
     fft = 5 * L * math.log2(L)
     return s * (m * (fft + 6 * L + 3 * v) + fft)
@@ -180,7 +181,7 @@ def main():
                    "path": "overlap-save FDFIR + |y|^2, one fused launch"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "nominal_tflops": nominal_flops(n, m, L, k_max) / (ms * 1e-3) / 1e12,
+        "nominal_tflops": nominal_flops(n, m, L, plan.info.valid_per_seg) / (ms * 1e-3) / 1e12,
     }
 
     if not args.no_tdfir:

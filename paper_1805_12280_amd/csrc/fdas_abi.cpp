@@ -60,7 +60,7 @@ int perm_dispatch(int L, int tau, int e)
 struct fdas_plan {
     int device = 0;
     int num_cu = 0;
-    int32_t M = 0, k_max = 0, L = 0, V = 0, kp = 0;
+    int32_t M = 0, k_max = 0, L = 0, D = 0, V = 0, kp = 0;
     int64_t input_len = 0;
     uint32_t flags = 0;
     int fused_per_cu = 1;
@@ -138,7 +138,10 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     p->M = M;
     p->k_max = K_max;
     p->L = L;
-    p->V = L - (K_max - 1);
+    // discard D >= K_max - 1 points per segment, rounded up to 32 outputs so
+    // every segment's kept outputs start on a 128-byte line
+    p->D = (K_max - 1 + 31) / 32 * 32;
+    p->V = L - p->D;
     p->kp = (K_max + 7) / 8 * 8;
     p->input_len = input_len;
     p->flags = flags;
@@ -215,7 +218,7 @@ FDAS_API int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, f
     a.H = plan->d_H;
     a.twL = plan->d_tw;
     a.M = plan->M;
-    a.head = plan->k_max - 1;
+    a.D = plan->D;
     a.V = plan->V;
     a.L = plan->L;
     a.items = (n + plan->V - 1) / plan->V * plan->M;

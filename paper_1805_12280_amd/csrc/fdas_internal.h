@@ -17,7 +17,7 @@ struct FusedArgs {
     int64_t n;
     const void *H;        // complex64 [M][L], permuted order
     const c32 *twL;       // complex64 [L]
-    int M, head, V, L;
+    int M, D, V, L;       // D: discarded points per segment, V = L - D kept
     int64_t items;        // S * M
     int64_t grid;         // workgroups
     float *P;

@@ -64,66 +64,86 @@ __global__ void tspec_kernel(const c32 *__restrict__ taps, const int *__restrict
 // workgroup takes one contiguous range of items, so it transforms a segment
 // forward once and reuses the spectrum for every template of that segment
 // in its range.
+//
+// Segment s covers input points [s V - D, s V - D + L); its points j >= D are
+// outputs s V + j - D.  D >= K_max - 1 (the overlap of Alg. 2, rounded up to
+// a multiple of 32 so each segment's outputs start on a 128-byte line) and
+// V = L - D.  Two LDS buffers (one per exchange) need two barriers per
+// inverse transform; the template spectra of the next item are loaded into
+// registers while the current item is transformed.
 template <int L>
-__global__ __launch_bounds__(L / 16) void fdfir_fused_kernel(
+__global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
     const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ H, const c32 *__restrict__ twL,
-    int M, int head, int V, int64_t items, float *__restrict__ P, int64_t ld)
+    int M, int D, int V, int64_t items, float *__restrict__ P, int64_t ld)
 {
     using SG = Seg<L>;
     constexpr int T = SG::T;
-    __shared__ c32 lds[SG::LDS_ELEMS];
+    __shared__ c32 bufA[SG::LDS_ELEMS];   // pass-0 <-> pass-1 exchange
+    __shared__ c32 bufC[SG::LDS_ELEMS];   // pass-1 <-> pass-2 exchange
     const int tau = threadIdx.x;
     const int64_t nb = gridDim.x, b = blockIdx.x;
     const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
     if (u0 >= u1) return;
 
-    c32 tw1[16], tw2[16];
-    SG::inv_twiddles(tau, twL, tw1, tw2);
+    c32 tw0[16], tw1[16];
+    SG::twiddles(tau, twL, tw0, tw1);
 
+    int64_t s = u0 / M;
+    int t = (int)(u0 - s * M);
+    c32 Hn[16];                            // spectra of the template of item u
+    {
+        const c32 *Ht = H + (int64_t)t * L;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
+    }
     c32 X[16];
     int64_t cur = -1;
     for (int64_t u = u0; u < u1; ++u) {
-        const int64_t s = u / M;
-        const int t = (int)(u - s * M);
-        // input index of segment point j is base + j; it is also the output
-        // index of point j, which is kept when j >= head = K_max - 1
-        const int64_t base = s * V - head;
+        const int64_t base = s * V - D;        // input/output index of segment point 0
         if (s != cur) {
             cur = s;
+            const c32 *xs = x + base;           // uniform; read only inside [0, n)
+            const int lo = (int)max<int64_t>(0, -base), hi = (int)min<int64_t>(L, n - base);
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
-                const int64_t i = base + tau + T * m;
-                X[m] = (i >= 0 && i < n) ? x[i] : mk(0.f, 0.f);
+                const int j = tau + T * m;
+                X[m] = (j >= lo && j < hi) ? xs[j] : mk(0.f, 0.f);
             }
-            SG::fwd0(tau, X, twL);
+            SG::fwd0(tau, X, tw0);
+            __syncthreads();                    // bufA/bufC free (previous item done)
+            SG::put_a(tau, X, bufA);
             __syncthreads();
-            SG::put_a(tau, X, lds);
+            SG::fwd1(tau, X, bufA, tw1);
+            SG::put_c(tau, X, bufC);
             __syncthreads();
-            SG::fwd1(tau, X, lds, twL);
-            __syncthreads();
-            SG::put_c(tau, X, lds);
-            __syncthreads();
-            SG::fwd2(tau, X, lds);
+            SG::fwd2(tau, X, bufC);
+            __syncthreads();                    // bufC reads done before inv2 rewrites it
         }
         c32 v[16];
-        const c32 *Ht = H + (int64_t)t * L + tau;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = mul(X[e], Ht[e * T]);
+        for (int e = 0; e < 16; ++e) v[e] = mul(X[e], Hn[e]);
+        // next item's template spectra, in flight during this transform
+        const int tn = (t + 1 == M) ? 0 : t + 1;
+        if (u + 1 < u1) {
+            const c32 *Ht = H + (int64_t)tn * L;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
+        }
+        SG::inv2(tau, v, bufC);
         __syncthreads();
-        SG::inv2(tau, v, lds, tw2);
+        SG::inv1(tau, v, bufC, tw1);
+        SG::put_a_inv(tau, v, bufA);
         __syncthreads();
-        SG::inv1(tau, v, lds, tw1);
-        __syncthreads();
-        SG::put_a_inv(tau, v, lds);
-        __syncthreads();
-        SG::inv0(tau, v, lds);
-        float *Pt = P + (int64_t)t * ld;
+        SG::inv0(tau, v, bufA, tw0);
+        float *Pt = P + (int64_t)t * ld + base;     // uniform; written only at j >= D
+        const int hi = (int)min<int64_t>(L, n - base);
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int j = tau + T * m;
-            const int64_t o = base + j;
-            if (j >= head && o < n) __builtin_nontemporal_store(norm2(v[m]), Pt + o);
+            if (j >= D && j < hi) __builtin_nontemporal_store(norm2(v[m]), Pt + j);
         }
+        t = tn;
+        if (t == 0) ++s;
     }
 }
 
@@ -142,14 +162,15 @@ __global__ __launch_bounds__(L / 16) void segfft_kernel(const c32 *__restrict__ 
     const int tau = threadIdx.x;
     const c32 *src = in + (int64_t)blockIdx.x * L;
     c32 *dst = out + (int64_t)blockIdx.x * L;
-    c32 v[16];
+    c32 v[16], tw0[16], tw1[16];
+    SG::twiddles(tau, twL, tw0, tw1);
     if (DIR < 0) {
 #pragma unroll
         for (int m = 0; m < 16; ++m) v[m] = src[tau + T * m];
-        SG::fwd0(tau, v, twL);
+        SG::fwd0(tau, v, tw0);
         SG::put_a(tau, v, lds);
         __syncthreads();
-        SG::fwd1(tau, v, lds, twL);
+        SG::fwd1(tau, v, lds, tw1);
         __syncthreads();
         SG::put_c(tau, v, lds);
         __syncthreads();
@@ -157,17 +178,15 @@ __global__ __launch_bounds__(L / 16) void segfft_kernel(const c32 *__restrict__ 
 #pragma unroll
         for (int e = 0; e < 16; ++e) dst[SG::perm(tau, e)] = v[e];
     } else {
-        c32 tw1[16], tw2[16];
-        SG::inv_twiddles(tau, twL, tw1, tw2);
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = src[SG::perm(tau, e)];
-        SG::inv2(tau, v, lds, tw2);
+        SG::inv2(tau, v, lds);
         __syncthreads();
         SG::inv1(tau, v, lds, tw1);
         __syncthreads();
         SG::put_a_inv(tau, v, lds);
         __syncthreads();
-        SG::inv0(tau, v, lds);
+        SG::inv0(tau, v, lds, tw0);
 #pragma unroll
         for (int m = 0; m < 16; ++m) dst[tau + T * m] = v[m];
     }
@@ -255,35 +274,36 @@ hipError_t launch_tspec(const c32 *taps, const int *tap_len, int kp, int M, int 
     return hipGetLastError();
 }
 
-int fused_blocks_per_cu(int L)
+template <int L> static int blocks_per_cu_of()
 {
     int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (L) {
-    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<1024>, 1024 / 16, 0); break;
-    case 2048: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<2048>, 2048 / 16, 0); break;
-    case 4096: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<4096>, 4096 / 16, 0); break;
-    default: break;
-    }
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_fused_kernel<L>, L / 16, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+int fused_blocks_per_cu(int L)
+{
+    switch (L) {
+    case 1024: return blocks_per_cu_of<1024>();
+    case 2048: return blocks_per_cu_of<2048>();
+    case 4096: return blocks_per_cu_of<4096>();
+    default: return 1;
+    }
+}
+
+template <int L> static void launch_fused_t(const FusedArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((fdfir_fused_kernel<L>), dim3((unsigned)a.grid), dim3(L / 16), 0, st,
+                       (const c32 *)a.x, a.n, (const c32 *)a.H, (const c32 *)a.twL, a.M, a.D,
+                       a.V, a.items, a.P, a.ld);
 }
 
 hipError_t launch_fused(const FusedArgs &a, hipStream_t st)
 {
-    dim3 grid((unsigned)a.grid), blk(a.L / 16);
     switch (a.L) {
-    case 1024:
-        hipLaunchKernelGGL(fdfir_fused_kernel<1024>, grid, blk, 0, st, (const c32 *)a.x, a.n,
-                           (const c32 *)a.H, (const c32 *)a.twL, a.M, a.head, a.V, a.items, a.P, a.ld);
-        break;
-    case 2048:
-        hipLaunchKernelGGL(fdfir_fused_kernel<2048>, grid, blk, 0, st, (const c32 *)a.x, a.n,
-                           (const c32 *)a.H, (const c32 *)a.twL, a.M, a.head, a.V, a.items, a.P, a.ld);
-        break;
-    case 4096:
-        hipLaunchKernelGGL(fdfir_fused_kernel<4096>, grid, blk, 0, st, (const c32 *)a.x, a.n,
-                           (const c32 *)a.H, (const c32 *)a.twL, a.M, a.head, a.V, a.items, a.P, a.ld);
-        break;
+    case 1024: launch_fused_t<1024>(a, st); break;
+    case 2048: launch_fused_t<2048>(a, st); break;
+    case 4096: launch_fused_t<4096>(a, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

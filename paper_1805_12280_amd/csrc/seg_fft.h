@@ -9,8 +9,8 @@
 //
 // Forward (decimation in frequency), natural-order input, work-item tau:
 //   pass 0  j = tau:            a[j][k1] = DFT16_m(w[j + T m]) * W_L^(j k1)
-//   pass 1  (k1, p) = tau:      c[k1][p][r] = DFT16_q(a[p + R2 q][k1]) * W_T^(p r)
-//   pass 2  (k1, p) = tau:      for g < G = 16/R2, r = p G + g:
+//   pass 1  tau = 16 p + k1:    c[k1][p][r] = DFT16_q(a[p + R2 q][k1]) * W_T^(p r)
+//   pass 2  tau = 16 p + k1:    for g < G = 16/R2, r = p G + g:
 //                               X[k1 + 16 r + 256 s] = DFT_R2,p'(c[k1][p'][r])
 // so after pass 2 the work-item holds X at the 16 frequencies perm(tau, e),
 // e = g R2 + s.  Like TOLS-FD, which multiplies in the FFT engine's own
@@ -20,9 +20,19 @@
 // natural-order output, so no reorder pass exists.
 //
 // Inverse (the transpose of the forward passes, conjugate twiddles):
-//   pass 2' per g: c'[k1][p'][r] = IDFT_R2,s(Z[k1 + 16 r + 256 s]) * W_T^-(p' r)
-//   pass 1'       b'[k1][p + R2 q] = IDFT16_r(c'[k1][p][r]) * W_L^-((p+R2 q) k1)
-//   pass 0'       y[j + T m] = IDFT16_k1(b'[k1][j])
+//   pass 2' per g: c'[k1][p'][r] = IDFT_R2,s(Z[k1 + 16 r + 256 s])
+//   pass 1'       b'[k1][p + R2 q] = IDFT16_r(c'[k1][p][r] * W_T^-(p r))
+//   pass 0'       y[j + T m] = IDFT16_k1(b'[k1][j] * W_L^-(j k1))
+// Each inverse twiddle is applied by the work-item that receives the value
+// after an LDS exchange, so it is the conjugate of the forward twiddle that
+// the same work-item applies: one register set of 2 x 16 twiddles serves
+// both directions.
+//
+// LDS: both exchanges use rows of T + 1 elements (an odd pitch).  With k1 the
+// fastest-varying index of the work-item in passes 1 and 2, every group of 16
+// neighbouring lanes touches 16 different rows, so each 8-byte access of a
+// wavefront is free of bank conflicts, and every address is a per-work-item
+// base plus a compile-time offset.
 //
 // Every function is __host__ __device__ so the index maps can be executed on
 // the CPU (one work-item after another between the barriers).
@@ -150,7 +160,7 @@ template <int L> struct Seg {
     static constexpr int T = L / 16;       // work-items per transform
     static constexpr int R2 = L / 256;     // radix of the last forward pass
     static constexpr int G = 16 / R2;      // last-pass butterflies per work-item
-    static constexpr int PAD = 4;          // LDS row padding (complex elements)
+    static constexpr int PAD = 1;          // LDS row padding (complex elements)
     static constexpr int ROW = T + PAD;
     static constexpr int LDS_ELEMS = 16 * ROW;
     static_assert(L == 1024 || L == 2048 || L == 4096, "segment length");
@@ -159,8 +169,8 @@ template <int L> struct Seg {
     FDAS_HD static int a_slot(int k1, int j) { return k1 * ROW + j; }
     FDAS_HD static int c_slot(int k1, int r, int p) { return k1 * ROW + r * R2 + p; }
 
-    FDAS_HD static int k1_of(int tau) { return tau / R2; }
-    FDAS_HD static int p_of(int tau) { return tau % R2; }
+    FDAS_HD static int k1_of(int tau) { return tau & 15; }
+    FDAS_HD static int p_of(int tau) { return tau >> 4; }
 
     // Frequency held by work-item tau in register e after the forward passes.
     FDAS_HD static int perm(int tau, int e)
@@ -169,27 +179,41 @@ template <int L> struct Seg {
         return k1_of(tau) + 16 * (p_of(tau) * G + g) + 256 * s;
     }
 
+    // Per-work-item twiddles, held in registers for the life of a workgroup:
+    //   tw0[k1] = W_L^(tau k1)   (pass 0, and conjugated in pass 0')
+    //   tw1[r]  = W_T^(p r)      (pass 1, and conjugated in pass 1')
+    // twL[e] = exp(-2 pi i e / L).  Index 0 is 1 and is never used.
+    FDAS_HD static void twiddles(int tau, const c32 *twL, c32 *tw0, c32 *tw1)
+    {
+        const int p = p_of(tau);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            tw0[k] = twL[(tau * k) & (L - 1)];
+            tw1[k] = twL[(16 * p * k) & (L - 1)];
+        }
+    }
+
     // -- forward --
-    // v[m] = w[tau + T m] on entry.  twL[e] = exp(-2 pi i e / L).
-    FDAS_HD static void fwd0(int tau, c32 *v, const c32 *twL)
+    // v[m] = w[tau + T m] on entry.
+    FDAS_HD static void fwd0(int tau, c32 *v, const c32 *tw0)
     {
         dft16<-1>(v);
 #pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) v[k1] = mul(v[k1], twL[(tau * k1) & (L - 1)]);
+        for (int k1 = 1; k1 < 16; ++k1) v[k1] = mul(v[k1], tw0[k1]);
     }
     FDAS_HD static void put_a(int tau, const c32 *v, c32 *lds)
     {
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) lds[a_slot(k1, tau)] = v[k1];
     }
-    FDAS_HD static void fwd1(int tau, c32 *v, const c32 *lds, const c32 *twL)
+    FDAS_HD static void fwd1(int tau, c32 *v, const c32 *lds, const c32 *tw1)
     {
         const int k1 = k1_of(tau), p = p_of(tau);
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = lds[a_slot(k1, p + R2 * q)];
         dft16<-1>(v);
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = mul(v[r], twL[(16 * p * r) & (L - 1)]);
+        for (int r = 1; r < 16; ++r) v[r] = mul(v[r], tw1[r]);
     }
     FDAS_HD static void put_c(int tau, const c32 *v, c32 *lds)
     {
@@ -213,21 +237,8 @@ template <int L> struct Seg {
     }
 
     // -- inverse --
-    // Per-work-item twiddles of the inverse passes (conjugates of twL):
-    //   tw2[g R2 + p'] = W_L^-(16 p' (p G + g)),  tw1[q] = W_L^-((p + R2 q) k1).
-    FDAS_HD static void inv_twiddles(int tau, const c32 *twL, c32 *tw1, c32 *tw2)
-    {
-        const int k1 = k1_of(tau), p = p_of(tau);
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int pp = 0; pp < R2; ++pp)
-                tw2[g * R2 + pp] = conj(twL[(16 * pp * (p * G + g)) & (L - 1)]);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) tw1[q] = conj(twL[((p + R2 * q) * k1) & (L - 1)]);
-    }
     // v[e] = Z[perm(tau, e)] on entry; writes c' to LDS.
-    FDAS_HD static void inv2(int tau, const c32 *v, c32 *lds, const c32 *tw2)
+    FDAS_HD static void inv2(int tau, const c32 *v, c32 *lds)
     {
         const int k1 = k1_of(tau), p = p_of(tau);
 #pragma unroll
@@ -236,19 +247,17 @@ template <int L> struct Seg {
 #pragma unroll
             for (int s = 0; s < R2; ++s) d[s] = v[g * R2 + s];
             dft<R2, +1>(d);
-            lds[c_slot(k1, p * G + g, 0)] = d[0];
 #pragma unroll
-            for (int pp = 1; pp < R2; ++pp) lds[c_slot(k1, p * G + g, pp)] = mul(d[pp], tw2[g * R2 + pp]);
+            for (int pp = 0; pp < R2; ++pp) lds[c_slot(k1, p * G + g, pp)] = d[pp];
         }
     }
     FDAS_HD static void inv1(int tau, c32 *v, const c32 *lds, const c32 *tw1)
     {
         const int k1 = k1_of(tau), p = p_of(tau);
+        v[0] = lds[c_slot(k1, 0, p)];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = lds[c_slot(k1, r, p)];
+        for (int r = 1; r < 16; ++r) v[r] = mul(lds[c_slot(k1, r, p)], conj(tw1[r]));
         dft16<+1>(v);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = mul(v[q], tw1[q]);
     }
     FDAS_HD static void put_a_inv(int tau, const c32 *v, c32 *lds)
     {
@@ -257,10 +266,11 @@ template <int L> struct Seg {
         for (int q = 0; q < 16; ++q) lds[a_slot(k1, p + R2 * q)] = v[q];
     }
     // v[m] = y[tau + T m] on exit.
-    FDAS_HD static void inv0(int tau, c32 *v, const c32 *lds)
+    FDAS_HD static void inv0(int tau, c32 *v, const c32 *lds, const c32 *tw0)
     {
+        v[0] = lds[a_slot(0, tau)];
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) v[k1] = lds[a_slot(k1, tau)];
+        for (int k1 = 1; k1 < 16; ++k1) v[k1] = mul(lds[a_slot(k1, tau)], conj(tw0[k1]));
         dft16<+1>(v);
     }
 };
