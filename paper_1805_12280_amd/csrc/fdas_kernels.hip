@@ -120,16 +120,15 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
             __syncthreads();                    // bufC reads done before inv2 rewrites it
         }
         c32 v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = mul(X[e], Hn[e]);
+        SG::inv2(tau, X, Hn, bufC);
         // next item's template spectra, in flight during this transform
+        // (after the last item this reads a valid row that is never used)
         const int tn = (t + 1 == M) ? 0 : t + 1;
-        if (u + 1 < u1) {
+        {
             const c32 *Ht = H + (int64_t)tn * L;
 #pragma unroll
             for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
         }
-        SG::inv2(tau, v, bufC);
         __syncthreads();
         SG::inv1(tau, v, bufC, tw1);
         SG::put_a_inv(tau, v, bufA);
@@ -137,10 +136,18 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
         SG::inv0(tau, v, bufA, tw0);
         float *Pt = P + (int64_t)t * ld + base;     // uniform; written only at j >= D
         const int hi = (int)min<int64_t>(L, n - base);
+        if (D <= T && hi == L) {
+            // segment inside the input and the discard within row 0:
+            // rows 1..15 are kept whole
+            if (tau >= D) __builtin_nontemporal_store(norm2(v[0]), Pt + tau);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int j = tau + T * m;
-            if (j >= D && j < hi) __builtin_nontemporal_store(norm2(v[m]), Pt + j);
+            for (int m = 1; m < 16; ++m) __builtin_nontemporal_store(norm2(v[m]), Pt + tau + T * m);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int j = tau + T * m;
+                if (j >= D && j < hi) __builtin_nontemporal_store(norm2(v[m]), Pt + j);
+            }
         }
         t = tn;
         if (t == 0) ++s;
@@ -178,9 +185,13 @@ __global__ __launch_bounds__(L / 16) void segfft_kernel(const c32 *__restrict__ 
 #pragma unroll
         for (int e = 0; e < 16; ++e) dst[SG::perm(tau, e)] = v[e];
     } else {
+        c32 one[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = src[SG::perm(tau, e)];
-        SG::inv2(tau, v, lds);
+        for (int e = 0; e < 16; ++e) {
+            v[e] = src[SG::perm(tau, e)];
+            one[e] = mk(1.f, 0.f);
+        }
+        SG::inv2(tau, v, one, lds);
         __syncthreads();
         SG::inv1(tau, v, lds, tw1);
         __syncthreads();

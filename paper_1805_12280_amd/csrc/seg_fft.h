@@ -82,6 +82,46 @@ template <int S, int E> FDAS_HD c32 rot16(c32 a)
     else return mul(a, w16<S, e>());
 }
 
+// ---- FMA forms of the butterfly with a multiplied operand ------------------
+// A radix-2 step with a multiplied operand, (A + w c, A - w c), takes four
+// FMAs for A + w c and two for A - w c = 2 A - (A + w c), instead of a
+// complex multiply (four) and a complex add and subtract (four).
+
+// a * w, or a * conj(w) when CJ
+template <bool CJ> FDAS_HD c32 cmul(c32 a, c32 w)
+{
+    const float wi = CJ ? -w.im : w.im;
+    return mk(a.re * w.re - a.im * wi, a.re * wi + a.im * w.re);
+}
+// A + c * w, or A + c * conj(w) when CJ
+template <bool CJ> FDAS_HD c32 cfma(c32 A, c32 w, c32 c)
+{
+    const float wi = CJ ? -w.im : w.im;
+    return mk(fmaf(-c.im, wi, fmaf(c.re, w.re, A.re)), fmaf(c.re, wi, fmaf(c.im, w.re, A.im)));
+}
+// 2 A - t
+FDAS_HD c32 twice_minus(c32 A, c32 t) { return mk(fmaf(2.f, A.re, -t.re), fmaf(2.f, A.im, -t.im)); }
+
+// radix-2 step (A + w c, A - w c) for a constant w = exp(S 2 pi i E / 16)
+template <int S, int E> FDAS_HD void rad2_const(c32 A, c32 c, c32 &sum, c32 &dif)
+{
+    constexpr int e = E & 15;
+    if constexpr (e == 0) { sum = add(A, c); dif = sub(A, c); }
+    else if constexpr (e == 4 || e == 8 || e == 12) { c32 r = rot16<S, e>(c); sum = add(A, r); dif = sub(A, r); }
+    else { sum = cfma<false>(A, w16<S, e>(), c); dif = twice_minus(A, sum); }
+}
+
+// Outputs of a 4-point DFT from its two radix-2 halves:
+// s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3.
+template <int S> FDAS_HD void dft4_join(c32 s02, c32 d02, c32 s13, c32 d13, c32 &X0, c32 &X1, c32 &X2, c32 &X3)
+{
+    const c32 r = mul_si<S>(d13);
+    X0 = add(s02, s13);
+    X2 = sub(s02, s13);
+    X1 = add(d02, r);
+    X3 = sub(d02, r);
+}
+
 // ---- small in-register DFTs, natural order in and out ----------------------
 
 template <int S> FDAS_HD void dft2(c32 *v)
@@ -93,32 +133,63 @@ template <int S> FDAS_HD void dft2(c32 *v)
 
 template <int S> FDAS_HD void dft4(c32 &x0, c32 &x1, c32 &x2, c32 &x3)
 {
-    c32 t0 = add(x0, x2), t1 = sub(x0, x2), t2 = add(x1, x3), t3 = mul_si<S>(sub(x1, x3));
-    x0 = add(t0, t2);
-    x2 = sub(t0, t2);
-    x1 = add(t1, t3);
-    x3 = sub(t1, t3);
+    dft4_join<S>(add(x0, x2), sub(x0, x2), add(x1, x3), sub(x1, x3), x0, x1, x2, x3);
 }
 
 template <int S> FDAS_HD void dft4v(c32 *v) { dft4<S>(v[0], v[1], v[2], v[3]); }
 
-// 8 = 2 x 4: n = 2 n1 + n2, k = k1 + 4 k2.
-template <int S> FDAS_HD void dft8(c32 *v)
+// 8 = 2 x 4: n = 2 n1 + n2, k = k1 + 4 k2.  Input: the radix-2 halves of the
+// two 4-point DFTs over n1 (pairs n1 = {0, 2} and {1, 3}) for n2 = 0, 1.
+template <int S> FDAS_HD void dft8_tail(const c32 *s, const c32 *d, c32 *v)
 {
-    c32 a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6];
-    c32 b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7];
-    dft4<S>(a0, a1, a2, a3);
-    dft4<S>(b0, b1, b2, b3);
-    b1 = rot16<S, 2>(b1);
-    b2 = rot16<S, 4>(b2);
-    b3 = rot16<S, 6>(b3);
-    v[0] = add(a0, b0); v[4] = sub(a0, b0);
-    v[1] = add(a1, b1); v[5] = sub(a1, b1);
-    v[2] = add(a2, b2); v[6] = sub(a2, b2);
-    v[3] = add(a3, b3); v[7] = sub(a3, b3);
+    // s[2 n2 + h], d[2 n2 + h]: h = 0 pairs (n1 0, 2), h = 1 pairs (n1 1, 3)
+    c32 a0, a1, a2, a3, b0, b1, b2, b3;
+    dft4_join<S>(s[0], d[0], s[1], d[1], a0, a1, a2, a3);
+    dft4_join<S>(s[2], d[2], s[3], d[3], b0, b1, b2, b3);
+    rad2_const<S, 0>(a0, b0, v[0], v[4]);
+    rad2_const<S, 2>(a1, b1, v[1], v[5]);
+    rad2_const<S, 4>(a2, b2, v[2], v[6]);
+    rad2_const<S, 6>(a3, b3, v[3], v[7]);
 }
 
-// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+template <int S> FDAS_HD void dft8(c32 *v)
+{
+    c32 s[4], d[4];
+#pragma unroll
+    for (int n2 = 0; n2 < 2; ++n2)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            s[2 * n2 + h] = add(v[2 * h + n2], v[2 * h + 4 + n2]);
+            d[2 * n2 + h] = sub(v[2 * h + n2], v[2 * h + 4 + n2]);
+        }
+    dft8_tail<S>(s, d, v);
+}
+
+// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.  The second layer: y[4 n2 + k1]
+// (first-layer outputs) times W16^(n2 k1), 4-point DFT over n2.
+template <int S> FDAS_HD void dft16_layer2(const c32 *y, c32 *v)
+{
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        c32 s02, d02, s13, d13, B;
+        // pair (n2 = 0, n2 = 2): y[k1] + W^(2 k1) y[8 + k1]
+        switch (k1) {
+        case 0: rad2_const<S, 0>(y[0], y[8], s02, d02); break;
+        case 1: rad2_const<S, 2>(y[1], y[9], s02, d02); break;
+        case 2: rad2_const<S, 4>(y[2], y[10], s02, d02); break;
+        default: rad2_const<S, 6>(y[3], y[11], s02, d02); break;
+        }
+        // pair (n2 = 1, n2 = 3): W^k1 y[4 + k1] + W^(3 k1) y[12 + k1]
+        switch (k1) {
+        case 0: rad2_const<S, 0>(y[4], y[12], s13, d13); break;
+        case 1: B = rot16<S, 1>(y[5]);  rad2_const<S, 3>(B, y[13], s13, d13); break;
+        case 2: B = rot16<S, 2>(y[6]);  rad2_const<S, 6>(B, y[14], s13, d13); break;
+        default: B = rot16<S, 3>(y[7]); rad2_const<S, 9>(B, y[15], s13, d13); break;
+        }
+        dft4_join<S>(s02, d02, s13, d13, v[k1], v[k1 + 4], v[k1 + 8], v[k1 + 12]);
+    }
+}
+
 template <int S> FDAS_HD void dft16(c32 *v)
 {
     c32 y[16];
@@ -131,19 +202,24 @@ template <int S> FDAS_HD void dft16(c32 *v)
         y[4 * n2 + 2] = c;
         y[4 * n2 + 3] = d;
     }
-    // twiddle W16^(n2 k1); y[4 n2 + k1]
-    y[5] = rot16<S, 1>(y[5]);   y[6] = rot16<S, 2>(y[6]);   y[7] = rot16<S, 3>(y[7]);
-    y[9] = rot16<S, 2>(y[9]);   y[10] = rot16<S, 4>(y[10]); y[11] = rot16<S, 6>(y[11]);
-    y[13] = rot16<S, 3>(y[13]); y[14] = rot16<S, 6>(y[14]); y[15] = rot16<S, 9>(y[15]);
+    dft16_layer2<S>(y, v);
+}
+
+// 16-point DFT of v[k] * tw[k] (tw[0] taken as 1; conj(tw) when CJ).
+template <int S, bool CJ> FDAS_HD void dft16_tw(c32 *v, const c32 *tw)
+{
+    c32 y[16];
 #pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) {
-        c32 a = y[k1], b = y[4 + k1], c = y[8 + k1], d = y[12 + k1];
-        dft4<S>(a, b, c, d);       // over n2 -> k2
-        v[k1] = a;
-        v[k1 + 4] = b;
-        v[k1 + 8] = c;
-        v[k1 + 12] = d;
+    for (int n2 = 0; n2 < 4; ++n2) {
+        const c32 A = n2 == 0 ? v[0] : cmul<CJ>(v[n2], tw[n2]);
+        const c32 s02 = cfma<CJ>(A, tw[8 + n2], v[8 + n2]);
+        const c32 d02 = twice_minus(A, s02);
+        const c32 B = cmul<CJ>(v[4 + n2], tw[4 + n2]);
+        const c32 s13 = cfma<CJ>(B, tw[12 + n2], v[12 + n2]);
+        const c32 d13 = twice_minus(B, s13);
+        dft4_join<S>(s02, d02, s13, d13, y[4 * n2], y[4 * n2 + 1], y[4 * n2 + 2], y[4 * n2 + 3]);
     }
+    dft16_layer2<S>(y, v);
 }
 
 template <int R, int S> FDAS_HD void dft(c32 *v)
@@ -152,6 +228,44 @@ template <int R, int S> FDAS_HD void dft(c32 *v)
     else if constexpr (R == 4) dft4v<S>(v);
     else if constexpr (R == 8) dft8<S>(v);
     else { static_assert(R == 16, "radix"); dft16<S>(v); }
+}
+
+// R-point DFT of the products a[k] * b[k] (the pointwise product of Alg. 2
+// folded into the first butterfly layer).
+template <int R, int S> FDAS_HD void dft_prod(const c32 *a, const c32 *b, c32 *v)
+{
+    // radix-2 pairs (k, k + R/2): A + a' b' and 2 A - (A + a' b'), A = a b
+    auto pair = [&](int i, int j, c32 &sum, c32 &dif) {
+        const c32 A = cmul<false>(a[i], b[i]);
+        sum = cfma<false>(A, b[j], a[j]);
+        dif = twice_minus(A, sum);
+    };
+    if constexpr (R == 2) {
+        pair(0, 1, v[0], v[1]);
+    } else if constexpr (R == 4) {
+        c32 s02, d02, s13, d13;
+        pair(0, 2, s02, d02);
+        pair(1, 3, s13, d13);
+        dft4_join<S>(s02, d02, s13, d13, v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        c32 s[4], d[4];
+#pragma unroll
+        for (int n2 = 0; n2 < 2; ++n2)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) pair(2 * h + n2, 2 * h + 4 + n2, s[2 * n2 + h], d[2 * n2 + h]);
+        dft8_tail<S>(s, d, v);
+    } else {
+        static_assert(R == 16, "radix");
+        c32 y[16];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            c32 s02, d02, s13, d13;
+            pair(n2, 8 + n2, s02, d02);
+            pair(4 + n2, 12 + n2, s13, d13);
+            dft4_join<S>(s02, d02, s13, d13, y[4 * n2], y[4 * n2 + 1], y[4 * n2 + 2], y[4 * n2 + 3]);
+        }
+        dft16_layer2<S>(y, v);
+    }
 }
 
 // ---- the three-pass segment transform -------------------------------------
@@ -237,16 +351,15 @@ template <int L> struct Seg {
     }
 
     // -- inverse --
-    // v[e] = Z[perm(tau, e)] on entry; writes c' to LDS.
-    FDAS_HD static void inv2(int tau, const c32 *v, c32 *lds)
+    // Z[perm(tau, e)] = X[e] * Hs[e] (the pointwise product, taken inside the
+    // first butterfly layer); writes c' to LDS.
+    FDAS_HD static void inv2(int tau, const c32 *X, const c32 *Hs, c32 *lds)
     {
         const int k1 = k1_of(tau), p = p_of(tau);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             c32 d[R2];
-#pragma unroll
-            for (int s = 0; s < R2; ++s) d[s] = v[g * R2 + s];
-            dft<R2, +1>(d);
+            dft_prod<R2, +1>(X + g * R2, Hs + g * R2, d);
 #pragma unroll
             for (int pp = 0; pp < R2; ++pp) lds[c_slot(k1, p * G + g, pp)] = d[pp];
         }
@@ -254,10 +367,9 @@ template <int L> struct Seg {
     FDAS_HD static void inv1(int tau, c32 *v, const c32 *lds, const c32 *tw1)
     {
         const int k1 = k1_of(tau), p = p_of(tau);
-        v[0] = lds[c_slot(k1, 0, p)];
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = mul(lds[c_slot(k1, r, p)], conj(tw1[r]));
-        dft16<+1>(v);
+        for (int r = 0; r < 16; ++r) v[r] = lds[c_slot(k1, r, p)];
+        dft16_tw<+1, true>(v, tw1);
     }
     FDAS_HD static void put_a_inv(int tau, const c32 *v, c32 *lds)
     {
@@ -268,10 +380,9 @@ template <int L> struct Seg {
     // v[m] = y[tau + T m] on exit.
     FDAS_HD static void inv0(int tau, c32 *v, const c32 *lds, const c32 *tw0)
     {
-        v[0] = lds[a_slot(0, tau)];
 #pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) v[k1] = mul(lds[a_slot(k1, tau)], conj(tw0[k1]));
-        dft16<+1>(v);
+        for (int k1 = 0; k1 < 16; ++k1) v[k1] = lds[a_slot(k1, tau)];
+        dft16_tw<+1, true>(v, tw0);
     }
 };
 
