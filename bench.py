@@ -27,7 +27,8 @@ METRIC = "template-samples/s (85 tpl x 2^22 pts) + HBM roofline frac; served p50
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector: 256 CU x 64 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 KERNEL_SOURCES = ("paper_1805_12280_amd/csrc/seg_fft.h", "paper_1805_12280_amd/csrc/fdas_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fdfir_fused_ska-85x2^22_L2048_traffic.md")
+TRAFFIC_FILES = {L: os.path.join(ROOT, "profiles", f"fdfir_fused_ska-85x2^22_L{L}_traffic.md")
+                 for L in (1024, 2048, 4096)}
 
 
 def log(*a):
@@ -42,12 +43,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; None otherwise."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(L):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary for this
+    segment length, if it was taken on the current kernel source; else None."""
+    path = TRAFFIC_FILES.get(L)
+    if path is None or not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
+    text = open(path).read()
     m_hash = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
@@ -114,14 +116,48 @@ def cpu_baseline_leg(w, P_gpu_rows_fn, target_s: float):
     }, {"rows": m, "outputs": n_s, "norm_err": st.norm_err, "rrmse": st.rrmse}
 
 
+def batched_leg(torch, fdas, steps, warmup):
+    """64 DM-trial spectra (2^19..2^22 points) x 85 templates per step, top-16
+    cells per array, the segment length picked by the autotuner, the call
+    captured once in a HIP graph and replayed."""
+    from paper_1805_12280_amd import autotune, datagen
+    log("generating the 64-array DM-trial batch ...")
+    batch = datagen.dm_trial_batch()
+    bank = batch.bank
+    dev = [torch.from_numpy(x).to("cuda:0") for x in batch.xs]
+    best, tuned = autotune.tune(bank, dev, mode="batched", topk=16, use_cache=False)
+    log(f"autotune (ms per batch): {tuned} -> L = {best}")
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(batch.lengths), seg_fft=best)
+    ws = torch.empty(plan.batched_workspace_bytes(batch.lengths, 16), dtype=torch.uint8, device="cuda:0")
+    out = torch.empty((len(dev), 16, 3), dtype=torch.int32, device="cuda:0")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        plan.convolve_batched(dev, topk=16, out=out, workspace=ws)
+    ms = time_calls(torch, g.replay, steps, warmup)
+    m = bank.num_templates
+    samples = m * sum(batch.lengths)
+    flops = sum(nominal_flops(n, m, best, bank.k_max) for n in batch.lengths)
+    tflops = flops / (ms * 1e-3) / 1e12
+    plan.close()
+    return {"workload": batch.name, "arrays": len(dev), "points": sum(batch.lengths),
+            "topk": 16, "seg_fft": best, "autotune_ms": tuned, "graph": True,
+            "ms_per_step": ms, "value": samples / (ms * 1e-3), "unit": "template-samples/s",
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--seg-fft", type=int, default=2048)
+    ap.add_argument("--seg-fft", type=int, default=0,
+                    help="segment length; 0 = pick with the autotuner among 1024/2048/4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tdfir", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling PMC byte counters)")
@@ -150,9 +186,16 @@ def main():
 
     log("generating the 85 x 2^22 workload ...")
     w = datagen.ska_workload()
-    m, n, L, k_max = w.bank.num_templates, w.n, args.seg_fft, w.bank.k_max
-    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=L)
+    m, n, k_max = w.bank.num_templates, w.n, w.bank.k_max
     x = torch.from_numpy(w.x).to(dev)
+    tuned = None
+    if args.seg_fft:
+        L = args.seg_fft
+    else:
+        from paper_1805_12280_amd import autotune
+        L, tuned = autotune.tune(w.bank, [x], mode="plane", use_cache=False)
+        log(f"autotune (ms per call): {tuned} -> L = {L}")
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=L)
     out = torch.empty((m, n), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log(f"plan: {plan.info.as_dict()} variant={plan.variant}")
@@ -161,7 +204,7 @@ def main():
     value = m * n / (ms * 1e-3)
     abytes = algorithmic_bytes(n, m, L)
     achieved = abytes / (ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(L)
     tflops = nominal_flops(n, m, L, k_max) / (ms * 1e-3) / 1e12
     log(f"fdas_convolve: {ms:.4f} ms/step, {value:.4e} template-samples/s, {achieved:.1f} GB/s")
 
@@ -180,7 +223,7 @@ def main():
         "data": "synthetic (seeded complex Gaussian noise + 3 chirps at amplitude-SNR 8; "
                 "85 chirp templates z=-42..42)",
         "config": {"workload": w.name, "templates": m, "n": n, "k_max": k_max,
-                   "taps_total": int(w.bank.tap_len.sum()), "seg_fft": L,
+                   "taps_total": int(w.bank.tap_len.sum()), "seg_fft": L, "autotune_ms": tuned,
                    "path": "overlap-save FDFIR + |y|^2, one fused launch"},
         # the fused kernel is bound by VALU issue (counters: ~0.9 of one wave64
         # VALU instruction per CU per cycle), so its roofline is the FP32 vector
@@ -204,6 +247,11 @@ def main():
         log(f"fdas_tdfir: {td_ms:.3f} ms/step")
         plan.convolve(x, out=out)          # leave the FDFIR plane in `out`
         torch.cuda.synchronize()
+
+    if not args.no_batch:
+        result["batched"] = batched_leg(torch, fdas, max(3, args.steps // 4), 2)
+        log(f"batched: {result['batched']['ms_per_step']:.3f} ms/step, "
+            f"{result['batched']['value']:.3e} template-samples/s")
 
     if not args.no_cpu_baseline:
         log("CPU oracle leg ...")

@@ -12,10 +12,12 @@
  *     P_t[i] = Re(y_t[i])^2 + Im(y_t[i])^2        (power, Section 4.3)
  *
  * fdas_convolve reaches P by overlap-save on the input (Section 3.2.2,
- * Alg. 2): segments of L = seg_fft points overlapping by K_max-1, one forward
+ * Alg. 2): segments of L = seg_fft points overlapping by D >= K_max-1, one forward
  * FFT per segment shared by all templates, a pointwise product with the
  * pre-transformed templates, an inverse FFT per (segment, template), the
- * first K_max-1 points of each discarded, and |y|^2 written.  fdas_tdfir
+ * first D points of each discarded, and |y|^2 written (D is K_max-1
+ * rounded up to a multiple of 32, so every segment's outputs start on a
+ * 128-byte line; any D >= K_max-1 gives the exact result).  fdas_tdfir
  * evaluates Eq. (1) directly, with the taps processed in blocks (overlap-add
  * on the taps, Section 3.1.2, Alg. 1).  Both write the same plane.
  *
@@ -33,6 +35,7 @@
 #ifndef FDAS_H
 #define FDAS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -58,7 +61,7 @@ typedef struct fdas_plan fdas_plan;
 
 typedef struct {
     int32_t seg_fft;          /* L: points per segment transform */
-    int32_t valid_per_seg;    /* V = L - (K_max - 1): outputs kept per segment */
+    int32_t valid_per_seg;    /* V = L - D: outputs kept per segment */
     int64_t num_segments;     /* S = ceil(input_len / V) */
     int32_t k_max;            /* K_max */
     int32_t num_templates;    /* M */
@@ -132,6 +135,57 @@ int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, float *d_p
  */
 int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
                int64_t ld_power, void *hip_stream);
+
+/* ---- batched DM trials ------------------------------------------------- */
+
+#define FDAS_MAX_BATCH 128   /* arrays per fdas_convolve_batched call */
+#define FDAS_MAX_TOPK  32    /* candidates kept per array */
+
+/* One candidate of a power plane: template row, output bin, power. */
+typedef struct {
+    int32_t t;
+    int32_t bin;
+    float p;
+} fdas_cand;
+
+/*
+ * fdas_batched_workspace_bytes -- device workspace fdas_convolve_batched
+ * needs for this batch shape (host arguments only; nothing is launched).
+ *   n      host int64 [count], each in [1, input_len].
+ *   count  1 <= count <= FDAS_MAX_BATCH;  topk  1 <= topk <= FDAS_MAX_TOPK.
+ *   out    host size_t, receives the byte count.
+ * Errors: FDAS_EINVAL.
+ */
+int fdas_batched_workspace_bytes(const fdas_plan *plan, const int64_t *n, int32_t count,
+                                 int32_t topk, size_t *out);
+
+/*
+ * fdas_convolve_batched -- the hot path over many DM-trial spectra at once
+ * (Section 3: about 6000 trials per beam, each filtered by the same bank),
+ * in one persistent launch, with each array's power plane reduced on the
+ * fly to its topk largest cells instead of being written.
+ *
+ *   d_in       host array [count] of device complex64 pointers (8-byte
+ *              aligned), array a holding n[a] points.
+ *   n          host int64 [count], 1 <= n[a] <= input_len, n[a] < 2^31.
+ *   d_out      device fdas_cand [count][topk]: row a lists array a's topk
+ *              cells (t, bin) with the largest P_t[bin], ordered by P
+ *              descending, then t ascending, then bin ascending.  If an
+ *              array has fewer than topk cells (n[a] * M < topk) the
+ *              remainder is {-1, -1, -1.0f}.
+ *   d_workspace, workspace_bytes  device scratch of at least
+ *              fdas_batched_workspace_bytes(plan, n, count, topk) bytes,
+ *              256-byte aligned, owned by the caller; no state is kept in
+ *              it between calls.
+ * Asynchronous on hip_stream (two kernel launches, no copies, no memsets,
+ * no allocation), so the call can be captured into a HIP graph.  Calls
+ * that share a workspace must not overlap.
+ * Errors: FDAS_EINVAL (NULL/misaligned pointers, sizes out of range, or a
+ * workspace that is too small), FDAS_EHIP.
+ */
+int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_in, const int64_t *n,
+                          int32_t count, int32_t topk, fdas_cand *d_out, void *d_workspace,
+                          size_t workspace_bytes, void *hip_stream);
 
 /*
  * fdas_segment_fft -- the plan's L-point segment transform on its own,

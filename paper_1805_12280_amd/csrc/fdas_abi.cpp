@@ -64,6 +64,7 @@ struct fdas_plan {
     int64_t input_len = 0;
     uint32_t flags = 0;
     int fused_per_cu = 1;
+    int topk_per_cu = 1;
     c32 *d_H = nullptr;        // [M][L], permuted frequency order per template
     c32 *d_tw = nullptr;       // [L]
     c32 *d_taps = nullptr;     // [M][kp], zero beyond tap_len
@@ -192,6 +193,7 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "building template spectra"); }
 
     p->fused_per_cu = fdas::fused_blocks_per_cu(L);
+    p->topk_per_cu = fdas::topk_blocks_per_cu(L);
     *out = p;
     return FDAS_OK;
 }
@@ -254,6 +256,112 @@ FDAS_API int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, floa
     if (a.tiles > 0x7fffffffLL) return fail(FDAS_EINVAL, "n too large for one launch");
     hipError_t e = fdas::launch_tdfir(a, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "launching the TDFIR kernel");
+    return FDAS_OK;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Shape of one batched launch, computed on the host from the lengths alone.
+struct BatchShape {
+    fdas::BatchSet bs;
+    int64_t items = 0, grid = 0;
+    int max_slots = 0;
+    size_t off_hdr = 0, off_nslots = 0, bytes = 0;
+};
+
+int batch_shape(const fdas_plan *plan, const int64_t *n, int32_t count, int32_t topk, BatchShape &sh)
+{
+    if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    if (!n) return fail(FDAS_EINVAL, "n is NULL");
+    if (count < 1 || count > FDAS_MAX_BATCH)
+        return fail(FDAS_EINVAL, "count=%d outside [1, %d]", count, FDAS_MAX_BATCH);
+    if (topk < 1 || topk > FDAS_MAX_TOPK) return fail(FDAS_EINVAL, "topk=%d outside [1, %d]", topk, FDAS_MAX_TOPK);
+    std::memset(&sh.bs, 0, sizeof sh.bs);
+    sh.bs.count = count;
+    int64_t acc = 0;
+    for (int a = 0; a < count; ++a) {
+        if (n[a] < 1 || n[a] > plan->input_len || n[a] >= (int64_t(1) << 31))
+            return fail(FDAS_EINVAL, "n[%d]=%lld outside [1, input_len=%lld]", a, (long long)n[a],
+                        (long long)plan->input_len);
+        sh.bs.n[a] = n[a];
+        sh.bs.item_begin[a] = acc;
+        acc += (n[a] + plan->V - 1) / plan->V * plan->M;
+    }
+    sh.bs.item_begin[count] = acc;
+    sh.items = acc;
+    const int64_t resident = (int64_t)plan->topk_per_cu * std::max(1, plan->num_cu);
+    sh.grid = std::max<int64_t>(1, std::min(acc, resident));
+    // most arrays any workgroup's contiguous item range touches
+    int ms = 1, a0 = 0;
+    for (int64_t b = 0; b < sh.grid; ++b) {
+        const int64_t u0 = acc * b / sh.grid, u1 = acc * (b + 1) / sh.grid;
+        if (u0 >= u1) continue;
+        while (sh.bs.item_begin[a0 + 1] <= u0) ++a0;
+        int a1 = a0;
+        while (sh.bs.item_begin[a1 + 1] <= u1 - 1) ++a1;
+        ms = std::max(ms, a1 - a0 + 1);
+    }
+    sh.max_slots = ms;
+    const size_t lists = (size_t)sh.grid * ms;
+    sh.off_hdr = align_up(lists * topk * sizeof(fdas_cand));
+    sh.off_nslots = sh.off_hdr + align_up(lists * 2 * sizeof(int));
+    sh.bytes = sh.off_nslots + align_up((size_t)sh.grid * sizeof(int));
+    return FDAS_OK;
+}
+
+}  // namespace
+
+FDAS_API int fdas_batched_workspace_bytes(const fdas_plan *plan, const int64_t *n, int32_t count,
+                                          int32_t topk, size_t *out)
+{
+    g_last_error.clear();
+    if (!out) return fail(FDAS_EINVAL, "out is NULL");
+    BatchShape sh;
+    int rc = batch_shape(plan, n, count, topk, sh);
+    if (rc != FDAS_OK) return rc;
+    *out = sh.bytes;
+    return FDAS_OK;
+}
+
+FDAS_API int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_in, const int64_t *n,
+                                   int32_t count, int32_t topk, fdas_cand *d_out, void *d_workspace,
+                                   size_t workspace_bytes, void *hip_stream)
+{
+    g_last_error.clear();
+    BatchShape sh;
+    int rc = batch_shape(plan, n, count, topk, sh);
+    if (rc != FDAS_OK) return rc;
+    if (!d_in) return fail(FDAS_EINVAL, "d_in is NULL");
+    if (!d_out || ((uintptr_t)d_out) % 4) return fail(FDAS_EINVAL, "d_out is NULL or not 4-byte aligned");
+    if (!d_workspace || ((uintptr_t)d_workspace) % kAlign)
+        return fail(FDAS_EINVAL, "d_workspace is NULL or not %zu-byte aligned", kAlign);
+    if (workspace_bytes < sh.bytes)
+        return fail(FDAS_EINVAL, "workspace of %zu bytes, %zu needed", workspace_bytes, sh.bytes);
+    for (int a = 0; a < count; ++a) {
+        if (!d_in[a] || ((uintptr_t)d_in[a]) % 8) return fail(FDAS_EINVAL, "d_in[%d] is NULL or misaligned", a);
+        sh.bs.x[a] = (const c32 *)d_in[a];
+    }
+    fdas::TopkArgs a;
+    a.bs = &sh.bs;
+    a.H = plan->d_H;
+    a.twL = plan->d_tw;
+    a.M = plan->M;
+    a.D = plan->D;
+    a.V = plan->V;
+    a.L = plan->L;
+    a.K = topk;
+    a.items = sh.items;
+    a.grid = sh.grid;
+    a.stage = d_workspace;
+    a.hdr = (char *)d_workspace + sh.off_hdr;
+    a.nslots = (int *)((char *)d_workspace + sh.off_nslots);
+    a.max_slots = sh.max_slots;
+    a.out = d_out;
+    hipError_t e = fdas::launch_topk(a, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "launching the batched FDFIR kernels");
     return FDAS_OK;
 }
 

@@ -35,6 +35,31 @@ struct TdArgs {
     int64_t ld;
 };
 
+constexpr int MAX_BATCH = 128;              // FDAS_MAX_BATCH
+constexpr int TOPK_MAX = 32;                // FDAS_MAX_TOPK
+
+// Arrays of one batched call, passed by value as a kernel argument (so a
+// captured graph holds it without any copy node).
+struct BatchSet {
+    const c32 *x[MAX_BATCH];
+    int64_t n[MAX_BATCH];
+    int64_t item_begin[MAX_BATCH + 1];    // first item of each array; [count] = total
+    int count;
+};
+
+struct TopkArgs {
+    const BatchSet *bs;
+    const void *H;
+    const c32 *twL;
+    int M, D, V, L, K;
+    int64_t items, grid;
+    void *stage;          // Cand [grid][max_slots][K]
+    void *hdr;            // int2 [grid][max_slots]
+    int *nslots;          // int [grid]
+    int max_slots;
+    void *out;            // fdas_cand [count][K]
+};
+
 hipError_t launch_twiddles(c32 *twL, int L, hipStream_t st);
 hipError_t launch_tspec(const c32 *taps, const int *tap_len, int kp, int M, int L, c32 *H,
                         hipStream_t st);
@@ -43,6 +68,8 @@ hipError_t launch_fused(const FusedArgs &a, hipStream_t st);
 hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int L, const c32 *twL,
                          hipStream_t st);
 size_t tdfir_lds_bytes(int kp);
+int topk_blocks_per_cu(int L);
+hipError_t launch_topk(const TopkArgs &a, hipStream_t st);
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
 
 }  // namespace fdas

@@ -185,3 +185,37 @@ def random_case(seed: int, n: int, m: int, k_max: int, ragged: bool = True):
         v = rng.standard_normal(2 * int(tap_len[t]))
         taps[t, : tap_len[t]] = (v[0::2] + 1j * v[1::2]) / math.sqrt(2.0 * tap_len[t])
     return x, Bank(z=np.zeros(m), taps=taps, tap_len=tap_len)
+
+
+@dataclasses.dataclass(frozen=True)
+class Batch:
+    name: str
+    xs: tuple              # complex64 arrays of uneven lengths
+    bank: Bank
+    seg_fft: int
+    chirps: tuple          # per array, a tuple of Chirp
+
+    @property
+    def lengths(self):
+        return [int(x.shape[0]) for x in self.xs]
+
+
+BATCH_LENGTHS = (1 << 19, 1 << 20, 1 << 21, 1 << 22)
+
+
+def dm_trial_batch(count: int = 64, lengths=BATCH_LENGTHS, seed_index: int = 2,
+                   bank: Bank | None = None) -> Batch:
+    """A batch of DM-trial spectra: lengths drawn uniformly from `lengths`,
+    complex Gaussian noise plus 0-2 chirps each (amplitude-SNR 8 as in the
+    single-array workload, z0 uniform in [-40, 40]), the 85-template bank."""
+    noise_rng, param_rng = _streams(seed_index)
+    bank = make_bank(Z_SKA) if bank is None else bank
+    xs, chirps = [], []
+    for _ in range(count):
+        n = int(lengths[int(param_rng.integers(0, len(lengths)))])
+        nc = int(param_rng.integers(0, 3))
+        amp = math.sqrt(128.0 / n)
+        cs = tuple(_draw_chirps(param_rng, n, nc, bank.k_max, amp))
+        xs.append(make_spectrum(n, cs, noise_rng))
+        chirps.append(cs)
+    return Batch(f"dm-batch-{count}x85", tuple(xs), bank, 2048, tuple(chirps))

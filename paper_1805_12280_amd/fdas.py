@@ -18,7 +18,11 @@ FDAS_OK, FDAS_EINVAL, FDAS_ENOMEM, FDAS_EHIP, FDAS_EUNSUPPORTED = 0, 1, 2, 3, 4
 FDAS_FP32 = 0
 FDAS_TAPS_ON_DEVICE = 1
 
-EXPORTED = ("fdas_plan_create", "fdas_convolve", "fdas_tdfir", "fdas_segment_fft",
+MAX_BATCH = 128
+MAX_TOPK = 32
+
+EXPORTED = ("fdas_plan_create", "fdas_convolve", "fdas_tdfir", "fdas_batched_workspace_bytes",
+            "fdas_convolve_batched", "fdas_segment_fft",
             "fdas_plan_template_spectra", "fdas_plan_info", "fdas_plan_destroy",
             "fdas_strerror", "fdas_last_error", "fdas_variant_name")
 
@@ -60,6 +64,10 @@ def load_library(path: str = LIB_PATH):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, i64, vp, i64, vp]
         f.restype = ctypes.c_int
+    lib.fdas_batched_workspace_bytes.argtypes = [vp, vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdas_batched_workspace_bytes.restype = ctypes.c_int
+    lib.fdas_convolve_batched.argtypes = [vp, vp, vp, i32, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.fdas_convolve_batched.restype = ctypes.c_int
     lib.fdas_segment_fft.argtypes = [vp, vp, vp, i64, i32, vp]
     lib.fdas_segment_fft.restype = ctypes.c_int
     lib.fdas_plan_template_spectra.argtypes = [vp, vp]
@@ -93,6 +101,12 @@ def _stream_handle(stream):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def split_candidates(raw):
+    """(t, bin, p) views of a [count, topk, 3] candidate tensor."""
+    import torch
+    return raw[..., 0], raw[..., 1], raw[..., 2].view(torch.float32)
 
 
 class Plan:
@@ -191,6 +205,43 @@ class Plan:
         n, out = self._io(x, out)
         check(self._lib.fdas_tdfir(self._h, _ptr(x), n, _ptr(out), out.stride(0),
                                    _stream_handle(stream)))
+        return out
+
+    def batched_workspace_bytes(self, lengths, topk: int = 16) -> int:
+        ns = (ctypes.c_int64 * len(lengths))(*[int(v) for v in lengths])
+        out = ctypes.c_size_t()
+        check(self._lib.fdas_batched_workspace_bytes(self._h, ns, len(lengths), int(topk),
+                                                     ctypes.byref(out)))
+        return int(out.value)
+
+    def convolve_batched(self, xs, topk: int = 16, out=None, workspace=None, stream=None):
+        """Top-`topk` cells (t, bin, P) of each array's power plane, computed in
+        one persistent launch without writing the planes.
+
+        Returns an int32 tensor [count, topk, 3]; use `split_candidates` to
+        view it as (t, bin, p)."""
+        import torch
+        xs = list(xs)
+        for x in xs:
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64
+                    and x.dim() == 1 and x.is_contiguous()):
+                raise FdasError(FDAS_EINVAL, "each array must be a contiguous CUDA complex64 vector")
+        count = len(xs)
+        if count < 1 or count > MAX_BATCH:
+            raise FdasError(FDAS_EINVAL, f"batch of {count} arrays; 1..{MAX_BATCH} supported")
+        lengths = [x.shape[0] for x in xs]
+        need = self.batched_workspace_bytes(lengths, topk)
+        dev = xs[0].device
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        if out is None:
+            out = torch.empty((count, topk, 3), dtype=torch.int32, device=dev)
+        if out.dtype != torch.int32 or tuple(out.shape) != (count, topk, 3) or not out.is_contiguous():
+            raise FdasError(FDAS_EINVAL, "out must be a contiguous int32 [count, topk, 3] tensor")
+        ptrs = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+        ns = (ctypes.c_int64 * count)(*lengths)
+        check(self._lib.fdas_convolve_batched(self._h, ptrs, ns, count, int(topk), _ptr(out),
+                                              _ptr(workspace), workspace.numel(), _stream_handle(stream)))
         return out
 
     def segment_fft(self, x, direction: int = -1, stream=None):
