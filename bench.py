@@ -148,6 +148,78 @@ def batched_leg(torch, fdas, steps, warmup):
                          "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
 
 
+SERVED_BANKS = {"z10": tuple(range(-10, 11)), "z21": tuple(range(-21, 22)), "z42": tuple(range(-42, 43))}
+SERVED_LENGTHS = ((1 << 18, 0.5), (1 << 20, 0.3), (1 << 22, 0.2))
+
+
+def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
+    """Poisson arrivals of jobs (length 2^18/2^20/2^22 with p = 0.5/0.3/0.2,
+    bank of 21/43/85 templates), continuous batching on resident plans,
+    top-16 per job.  The saturated rate is measured first (all jobs present at
+    t = 0); then arrivals at fractions of it.  Inputs are resident spectra (the
+    stage before filtering runs on the device)."""
+    import numpy as np
+    from paper_1805_12280_amd import datagen
+    from paper_1805_12280_amd.serve import GpuExecutor, Job, Scheduler, latency_stats
+    rng = np.random.default_rng(seed)
+    banks = {k: datagen.make_bank(v) for k, v in SERVED_BANKS.items()}
+    pool = {}
+    noise_rng = np.random.default_rng(seed + 1)
+    for n, _ in SERVED_LENGTHS:
+        pool[n] = [torch.from_numpy(datagen.make_spectrum(n, (), noise_rng)).to("cuda:0") for _ in range(2)]
+    lens = [n for n, _ in SERVED_LENGTHS]
+    probs = [p for _, p in SERVED_LENGTHS]
+    ex = GpuExecutor(banks, input_len=1 << 22, topk=16, slots=3, seg_fft={k: 1024 for k in banks})
+    mfree, _ = torch.cuda.mem_get_info()
+    budget = int(0.25 * mfree)
+
+    def draw(count):
+        out = []
+        for i in range(count):
+            n = int(rng.choice(lens, p=probs))
+            bank = str(rng.choice(list(banks)))
+            out.append((i, bank, n, pool[n][int(rng.integers(0, 2))]))
+        return out
+
+    def run(spec, gaps):
+        sched = Scheduler(ex, budget, max_batch=16)
+        t = time.perf_counter()
+        jobs = []
+        for (i, bank, n, x), g in zip(spec, gaps):
+            t += g
+            jobs.append(Job(i, bank, x, n, t))
+        start = time.perf_counter()
+        pending = list(jobs)
+        while pending or not sched.idle:
+            now = time.perf_counter()
+            while pending and pending[0].arrival <= now:
+                sched.submit(pending.pop(0))
+            sched.step()
+        end = time.perf_counter()
+        samples = sum(j.n * banks[j.bank].num_templates for j in jobs)
+        st = latency_stats(jobs)
+        st.update({"makespan_s": end - start, "jobs_per_s": len(jobs) / (end - start),
+                   "template_samples_per_s": samples / (end - start),
+                   "mean_batch": float(np.mean(sched.batches))})
+        return st
+
+    warm = draw(16)
+    run(warm, [0.0] * len(warm))
+    spec = draw(jobs_per_rate)
+    sat = run(spec, [0.0] * len(spec))
+    lam = sat["jobs_per_s"]
+    out = {"saturated": sat, "rates": [], "slots": ex.slots, "max_batch": 16, "topk": 16,
+           "budget_bytes": budget, "jobs_per_rate": jobs_per_rate}
+    for r in rates:
+        gaps = rng.exponential(1.0 / (r * lam), size=len(spec)).tolist()
+        st = run(spec, gaps)
+        st["offered_fraction"] = r
+        st["offered_jobs_per_s"] = r * lam
+        out["rates"].append(st)
+    ex.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tdfir", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling PMC byte counters)")
@@ -252,6 +325,14 @@ def main():
         result["batched"] = batched_leg(torch, fdas, max(3, args.steps // 4), 2)
         log(f"batched: {result['batched']['ms_per_step']:.3f} ms/step, "
             f"{result['batched']['value']:.3e} template-samples/s")
+
+    if not args.no_served:
+        result["served"] = served_leg(torch)
+        log("served: " + json.dumps({k: (round(v, 3) if isinstance(v, float) else v)
+                                     for k, v in result["served"]["saturated"].items()}))
+        for st in result["served"]["rates"]:
+            log(f"  offered {st['offered_fraction']:.2f} x saturated: p50 {st['p50_ms']:.2f} ms, "
+                f"p99 {st['p99_ms']:.2f} ms, {st['jobs_per_s']:.0f} jobs/s")
 
     if not args.no_cpu_baseline:
         log("CPU oracle leg ...")

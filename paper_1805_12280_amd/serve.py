@@ -1,0 +1,204 @@
+"""Served FT convolution: a continuous-batching request loop.
+
+Jobs (one DM-trial spectrum each, against one of several resident template
+banks) arrive over time; the server keeps one plan per bank resident on the
+device, admits jobs while their device footprint fits a budget, and, whenever
+an execution slot (a stream) is free, launches the oldest admitted jobs of
+one bank as a single batched call (fdas_convolve_batched: one persistent
+launch over all their segments and templates, each spectrum reduced to its
+top-K cells).  Several slots run at once, so work admitted while other
+batches are on the device overlaps with them; a batch's footprint is
+released when its completion event has fired.
+
+The scheduler is plain Python over a small executor interface, so its policy
+(admission, batching, ordering, latency accounting) runs on the CPU against
+any executor; GpuExecutor is the one that drives the library.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+
+@dataclasses.dataclass
+class Job:
+    job_id: int
+    bank: str
+    x: object                   # the spectrum (a CUDA complex64 tensor for GpuExecutor)
+    n: int
+    arrival: float              # scheduler clock time of arrival
+    admitted: float | None = None
+    started: float | None = None
+    done: float | None = None
+    result: object = None       # per-job candidates [topk, 3] (t, bin, p bits)
+
+    @property
+    def latency(self):
+        return None if self.done is None else self.done - self.arrival
+
+
+class Scheduler:
+    """Continuous batching with admission by device footprint.
+
+    executor: object with
+        slots                       number of batches that may run at once
+        footprint(bank, n) -> int   device bytes a job holds while admitted
+        start(bank, jobs) -> token  launch one batched call (non-blocking)
+        poll(token) -> bool         True once the call has finished
+        finish(token) -> list       per-job results, in the order given
+    budget_bytes: admitted jobs' footprints never exceed this.
+    max_batch: jobs per batched call.
+    """
+
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 16, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.waiting = collections.deque()               # arrived, not admitted
+        self.admitted = collections.OrderedDict()        # bank -> deque of jobs
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.running = []                                # (token, bank, jobs, bytes)
+        self.completed = []
+        self.batches = []                                # sizes of launched batches
+
+    # -- intake ---------------------------------------------------------------
+    def submit(self, job: Job):
+        fp = self.ex.footprint(job.bank, job.n)
+        if fp > self.budget:
+            raise ValueError(f"job {job.job_id} needs {fp} bytes, budget is {self.budget}")
+        self.waiting.append(job)
+
+    def _admit(self):
+        now = self.clock()
+        while self.waiting:
+            job = self.waiting[0]
+            fp = self.ex.footprint(job.bank, job.n)
+            if self.in_use + fp > self.budget:
+                break                                    # FIFO: later jobs wait too
+            self.waiting.popleft()
+            self.in_use += fp
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            job.admitted = now
+            self.admitted.setdefault(job.bank, collections.deque()).append(job)
+
+    def _launch(self):
+        while len(self.running) < self.ex.slots:
+            # the bank whose oldest admitted job arrived first
+            best = None
+            for bank, q in self.admitted.items():
+                if q and (best is None or q[0].arrival < self.admitted[best][0].arrival):
+                    best = bank
+            if best is None:
+                return
+            q = self.admitted[best]
+            jobs = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
+            now = self.clock()
+            for j in jobs:
+                j.started = now
+            token = self.ex.start(best, jobs)
+            nbytes = sum(self.ex.footprint(best, j.n) for j in jobs)
+            self.running.append((token, best, jobs, nbytes))
+            self.batches.append(len(jobs))
+
+    def _reap(self):
+        still = []
+        for token, bank, jobs, nbytes in self.running:
+            if self.ex.poll(token):
+                now = self.clock()
+                for j, r in zip(jobs, self.ex.finish(token)):
+                    j.result = r
+                    j.done = now
+                    self.completed.append(j)
+                self.in_use -= nbytes
+            else:
+                still.append((token, bank, jobs, nbytes))
+        self.running = still
+
+    def step(self):
+        """One scheduler pass: retire finished batches, admit, launch."""
+        self._reap()
+        self._admit()
+        self._launch()
+
+    @property
+    def idle(self):
+        return not (self.waiting or self.running or any(self.admitted.values()))
+
+    def drain(self, sleep_s: float = 0.0):
+        while not self.idle:
+            self.step()
+            if sleep_s:
+                time.sleep(sleep_s)
+
+
+def latency_stats(jobs):
+    lat = sorted(j.latency for j in jobs if j.latency is not None)
+    if not lat:
+        return {"count": 0}
+    pick = lambda q: lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]   # noqa: E731
+    return {"count": len(lat), "p50_ms": 1e3 * pick(0.50), "p99_ms": 1e3 * pick(0.99),
+            "mean_ms": 1e3 * sum(lat) / len(lat), "max_ms": 1e3 * lat[-1]}
+
+
+class GpuExecutor:
+    """Batched calls on `slots` streams, with one resident plan per bank."""
+
+    def __init__(self, banks: dict, input_len: int, topk: int = 16, slots: int = 2,
+                 seg_fft: dict | None = None, device: str = "cuda:0"):
+        import torch
+        from . import fdas
+        self.torch = torch
+        self.fdas = fdas
+        self.topk = int(topk)
+        self.slots = int(slots)
+        self.device = torch.device(device)
+        self.plans = {}
+        for name, bank in banks.items():
+            L = (seg_fft or {}).get(name, 2048)
+            self.plans[name] = fdas.Plan(bank.taps, bank.tap_len, input_len=input_len, seg_fft=L)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.slots)]
+        self.free_streams = list(range(self.slots))
+        # per-stream workspace and candidate buffers, grown on demand and then
+        # reused, so the steady-state loop allocates nothing
+        self.ws = [None] * self.slots
+        self.outs = [None] * self.slots
+
+    def footprint(self, bank, n):
+        # the spectrum while it is admitted, its share of the batch workspace
+        # (bounded by one candidate list per workgroup), and its candidates
+        return 8 * int(n) + 64 * 1024 + 12 * self.topk
+
+    def start(self, bank, jobs):
+        torch = self.torch
+        sid = self.free_streams.pop()
+        st = self.streams[sid]
+        plan = self.plans[bank]
+        need = plan.batched_workspace_bytes([j.n for j in jobs], self.topk)
+        if self.ws[sid] is None or self.ws[sid].numel() < need:
+            self.ws[sid] = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=self.device)
+        if self.outs[sid] is None or self.outs[sid].shape[0] < len(jobs):
+            self.outs[sid] = torch.empty((max(len(jobs), 16), self.topk, 3), dtype=torch.int32,
+                                         device=self.device)
+        out = self.outs[sid][:len(jobs)]
+        st.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(st):
+            plan.convolve_batched([j.x for j in jobs], topk=self.topk, out=out, workspace=self.ws[sid])
+            res = out.clone()
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return (sid, ev, res, jobs)
+
+    def poll(self, token):
+        return token[1].query()
+
+    def finish(self, token):
+        sid, ev, res, jobs = token
+        self.free_streams.append(sid)
+        return [res[i] for i in range(len(jobs))]
+
+    def close(self):
+        for p in self.plans.values():
+            p.close()
