@@ -182,7 +182,7 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
         return out
 
     def run(spec, gaps):
-        sched = Scheduler(ex, budget, max_batch=16)
+        sched = Scheduler(ex, budget, max_batch=16, max_wait_s=2e-3)
         t = time.perf_counter()
         jobs = []
         for (i, bank, n, x), g in zip(spec, gaps):
@@ -208,7 +208,7 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
     spec = draw(jobs_per_rate)
     sat = run(spec, [0.0] * len(spec))
     lam = sat["jobs_per_s"]
-    out = {"saturated": sat, "rates": [], "slots": ex.slots, "max_batch": 16, "topk": 16,
+    out = {"saturated": sat, "rates": [], "slots": ex.slots, "max_batch": 16, "max_wait_ms": 2.0, "topk": 16,
            "budget_bytes": budget, "jobs_per_rate": jobs_per_rate}
     for r in rates:
         gaps = rng.exponential(1.0 / (r * lam), size=len(spec)).tolist()
@@ -217,6 +217,42 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
         st["offered_jobs_per_s"] = r * lam
         out["rates"].append(st)
     ex.close()
+    return out
+
+
+def sweeps_leg(torch, fdas):
+    """The paper's experiment shapes on this GPU.
+    fig8: M = 84 filters of 421 taps, inputs 2^18..2^22, FDFIR + power; the
+          paper reports the average latency per filter (3xAOLS-2048-P on one
+          FPGA: 2.98 ms per filter at 2^22, Section 6.3).
+    fig7: one filter of 64/128/256/421 taps on 2^22 points, TDFIR vs FDFIR
+          (the paper's FPGA TD theoretical latency is 108-124 ms at 421 taps,
+          Table 4)."""
+    import numpy as np
+    from paper_1805_12280_amd import datagen
+    out = {"fig8": [], "fig7": []}
+    x_all, bank = datagen.random_case(421, 1 << 22, 84, 421, ragged=False)
+    x = torch.from_numpy(x_all).to("cuda:0")
+    for L in (1024, 2048):
+        plan = fdas.Plan(bank.taps, bank.tap_len, input_len=1 << 22, seg_fft=L)
+        for lg in range(18, 23):
+            n = 1 << lg
+            o = torch.empty((84, n), dtype=torch.float32, device="cuda:0")
+            ms = time_calls(torch, lambda: plan.convolve(x[:n], out=o), 5, 2)
+            out["fig8"].append({"n": n, "seg_fft": L, "filters": 84, "taps": 421, "ms": ms,
+                                "ms_per_filter": ms / 84, "template_samples_per_s": 84 * n / (ms * 1e-3)})
+            del o
+        plan.close()
+    for k in (64, 128, 256, 421):
+        h = bank.taps[:1, :k].copy()
+        h /= np.sqrt(np.sum(np.abs(h.astype(np.complex128)) ** 2))
+        plan = fdas.Plan(h, None, input_len=1 << 22, seg_fft=1024 if k <= 256 else 2048)
+        o = torch.empty((1, 1 << 22), dtype=torch.float32, device="cuda:0")
+        fd = time_calls(torch, lambda: plan.convolve(x, out=o), 10, 2)
+        td = time_calls(torch, lambda: plan.tdfir(x, out=o), 5, 1)
+        out["fig7"].append({"taps": k, "n": 1 << 22, "seg_fft": plan.seg_fft, "fdfir_ms": fd, "tdfir_ms": td,
+                            "tdfir_gflops": 8.0 * k * (1 << 22) / (td * 1e-3) / 1e9})
+        plan.close()
     return out
 
 
@@ -231,6 +267,7 @@ def main():
     ap.add_argument("--no-tdfir", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-sweeps", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling PMC byte counters)")
@@ -333,6 +370,14 @@ def main():
         for st in result["served"]["rates"]:
             log(f"  offered {st['offered_fraction']:.2f} x saturated: p50 {st['p50_ms']:.2f} ms, "
                 f"p99 {st['p99_ms']:.2f} ms, {st['jobs_per_s']:.0f} jobs/s")
+
+    if not args.no_sweeps:
+        result["sweeps"] = sweeps_leg(torch, fdas)
+        for r in result["sweeps"]["fig8"]:
+            log(f"fig8 84x421 n=2^{int(math.log2(r['n']))} L={r['seg_fft']}: {r['ms']:.3f} ms "
+                f"({r['ms_per_filter'] * 1e3:.1f} us per filter)")
+        for r in result["sweeps"]["fig7"]:
+            log(f"fig7 1x{r['taps']} taps: FDFIR {r['fdfir_ms']:.3f} ms, TDFIR {r['tdfir_ms']:.3f} ms")
 
     if not args.no_cpu_baseline:
         log("CPU oracle leg ...")

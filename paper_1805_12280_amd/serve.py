@@ -49,12 +49,18 @@ class Scheduler:
         finish(token) -> list       per-job results, in the order given
     budget_bytes: admitted jobs' footprints never exceed this.
     max_batch: jobs per batched call.
+    max_wait_s: while other batches are running, a batch smaller than
+        max_batch is held until its oldest job has waited this long, so light
+        load does not fragment the device into many one-job launches (an idle
+        device starts a batch at once).
     """
 
-    def __init__(self, executor, budget_bytes: int, max_batch: int = 16, clock=time.perf_counter):
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 16, max_wait_s: float = 0.0,
+                 clock=time.perf_counter):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
+        self.max_wait = float(max_wait_s)
         self.clock = clock
         self.waiting = collections.deque()               # arrived, not admitted
         self.admitted = collections.OrderedDict()        # bank -> deque of jobs
@@ -94,8 +100,10 @@ class Scheduler:
             if best is None:
                 return
             q = self.admitted[best]
-            jobs = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
             now = self.clock()
+            if self.running and len(q) < self.max_batch and now - q[0].arrival < self.max_wait:
+                return
+            jobs = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
             for j in jobs:
                 j.started = now
             token = self.ex.start(best, jobs)
@@ -162,7 +170,7 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.slots)]
         self.free_streams = list(range(self.slots))
         # per-stream workspace and candidate buffers, grown on demand and then
-        # reused, so the steady-state loop allocates nothing
+        # reused (each batch only allocates the small copy of its candidates)
         self.ws = [None] * self.slots
         self.outs = [None] * self.slots
 
@@ -177,14 +185,16 @@ class GpuExecutor:
         st = self.streams[sid]
         plan = self.plans[bank]
         need = plan.batched_workspace_bytes([j.n for j in jobs], self.topk)
-        if self.ws[sid] is None or self.ws[sid].numel() < need:
-            self.ws[sid] = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=self.device)
-        if self.outs[sid] is None or self.outs[sid].shape[0] < len(jobs):
-            self.outs[sid] = torch.empty((max(len(jobs), 16), self.topk, 3), dtype=torch.int32,
-                                         device=self.device)
-        out = self.outs[sid][:len(jobs)]
         st.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(st):
+            # allocated on the slot's own stream: a replaced buffer is only
+            # reused in that stream's order
+            if self.ws[sid] is None or self.ws[sid].numel() < need:
+                self.ws[sid] = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=self.device)
+            if self.outs[sid] is None or self.outs[sid].shape[0] < len(jobs):
+                self.outs[sid] = torch.empty((max(len(jobs), 16), self.topk, 3), dtype=torch.int32,
+                                             device=self.device)
+            out = self.outs[sid][:len(jobs)]
             plan.convolve_batched([j.x for j in jobs], topk=self.topk, out=out, workspace=self.ws[sid])
             res = out.clone()
             ev = torch.cuda.Event()

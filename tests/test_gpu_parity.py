@@ -176,3 +176,18 @@ def test_taps_on_device(torch_cuda, fdas, toy):
     x = torch.from_numpy(toy.x).cuda()
     assert torch.equal(p_host.convolve(x), p_dev.convolve(x))
     assert np.array_equal(p_host.template_spectra(), p_dev.template_spectra())
+
+
+@pytest.mark.parametrize("L", [1024, 2048])
+def test_paper_shape_84_filters_421_taps(torch_cuda, fdas, L):
+    """The paper's studied bank shape (84 complex filters of 421 taps,
+    Section 3), full plane at 2^16 points, FDFIR and TDFIR."""
+    x, bank = datagen.random_case(421, 1 << 16, 84, 421, ragged=False)
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=1 << 16, seg_fft=L)
+    for method in ("convolve", "tdfir"):
+        _say(f"[84x421] L={L} {method}")
+        P = run_plane(torch_cuda, plan, x, method)
+        st = compare(P, x, bank, 1 << 16, rows_per_block=28)
+        assert st.norm_err <= FP32_TOL, st.summary()
+        ok, bad = st.topk_agree()
+        assert ok, bad

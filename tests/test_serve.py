@@ -140,3 +140,16 @@ def test_latency_stats():
     js = [Job(i, "b", None, 1, 0.0, done=(i + 1) * 1e-3) for i in range(100)]
     st = latency_stats(js)
     assert st["count"] == 100 and abs(st["p50_ms"] - 50.5) < 1.0 and abs(st["p99_ms"] - 99.0) < 1.01
+
+
+def test_hold_small_batches_while_busy(banks):
+    """With max_wait, a small batch waits while the device is busy, so later
+    arrivals join it; an idle device starts at once."""
+    clock = FakeClock()
+    ex = OracleExecutor(banks, clock, slots=3, cost=1e-3)
+    sched = Scheduler(ex, 10 ** 9, max_batch=4, max_wait_s=0.05, clock=clock)
+    xs = [datagen.random_case(40 + i, 100, 1, 1)[0] for i in range(4)]
+    jobs = [Job(i, "b3", xs[i], 100, 0.001 * i) for i in range(4)]
+    run(jobs, ex, sched, clock, dt=1e-3)
+    assert sched.batches[0] == 1            # idle device: started at once
+    assert sched.batches[1] == 3            # the rest waited for each other
