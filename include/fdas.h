@@ -56,6 +56,8 @@ enum {
 /* ---- plan flags -------------------------------------------------------- */
 #define FDAS_FP32            0u          /* float32 storage and arithmetic */
 #define FDAS_TAPS_ON_DEVICE  (1u << 0)   /* `taps` and `tap_len` are device pointers */
+#define FDAS_FP16            (1u << 1)   /* 16-bit IEEE storage, matrix-core inverse FFT */
+#define FDAS_BF16            (1u << 2)   /* bfloat16 storage, matrix-core inverse FFT */
 
 typedef struct fdas_plan fdas_plan;
 
@@ -88,8 +90,19 @@ typedef struct {
  *   K_max      taps per row of `taps`, >= 1 and <= seg_fft / 2.
  *   input_len  largest input length the plan will be given, >= 1.
  *   seg_fft    L in {1024, 2048, 4096}, or 0 for the default 2048.
- *   flags      FDAS_FP32, optionally | FDAS_TAPS_ON_DEVICE; anything else
- *              returns FDAS_EUNSUPPORTED.
+ *   flags      FDAS_FP32, FDAS_FP16 or FDAS_BF16, optionally |
+ *              FDAS_TAPS_ON_DEVICE; anything else returns FDAS_EUNSUPPORTED.
+ *              FDAS_FP16/FDAS_BF16 ("mixed" plans): the input spectrum and the
+ *              template spectra are stored in 16 bits (round to nearest even;
+ *              the spectra scaled by a power of two so their largest
+ *              component is in [1/2, 1)); the forward FFT runs in float32 and
+ *              the inverse FFT passes run on the matrix cores with 16-bit
+ *              operands and float32 accumulation, each segment scaled by a
+ *              power of two; the power plane is float32.  Mixed plans need
+ *              seg_fft = 2048 (or 0) and support fdas_convolve only; the
+ *              other calls return FDAS_EUNSUPPORTED.  A mixed plan also
+ *              holds a staging buffer of 16 KB per segment of input_len for
+ *              the scaled segment spectra of one call.
  *   hip_stream stream on which the plan is built; the call waits for that
  *              work before it returns, so the plan is ready on any stream.
  *
@@ -111,7 +124,9 @@ int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *tap_len,
  * of Section 4.3), one launch for all M templates.
  *
  *   plan       from fdas_plan_create (not NULL).
- *   d_in       device complex64 [n], 8-byte aligned.
+ *   d_in       device complex64 [n], 8-byte aligned; for a mixed plan, pairs
+ *              (re, im) of 16-bit numbers (binary16 or bfloat16), 4-byte
+ *              aligned.
  *   n          1 <= n <= input_len.
  *   d_power    device float32, M rows of ld_power floats, 4-byte aligned;
  *              row t receives P_t[0..n).  Columns n..ld_power-1 are not
@@ -120,8 +135,12 @@ int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *tap_len,
  *   hip_stream stream to enqueue on.
  *
  * Asynchronous: returns after enqueueing; the caller keeps d_in and d_power
- * alive until the stream has run the work.  The plan is read-only here, so
- * one plan may be used from several streams at once.
+ * alive until the stream has run the work.  A float32 plan is read-only
+ * here, so one plan may be used from several streams at once.  A mixed plan
+ * runs two launches (forward transforms and scales of all segments into the
+ * plan's staging buffer, then the template loop) and orders its calls: each
+ * call's work waits, on its stream, for the previous call's work on the same
+ * plan, whichever stream that ran on.
  * Errors: FDAS_EINVAL (NULL or misaligned pointers, n or ld_power out of
  * range), FDAS_EHIP (launch failure).
  */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,8 @@ int hip_fail(hipError_t e, const char *what)
 }
 
 constexpr int kVariantFusedPersistent = 1;
+constexpr int kVariantMixedFp16 = 2;
+constexpr int kVariantMixedBf16 = 3;
 
 bool supported_l(int L) { return L == 1024 || L == 2048 || L == 4096; }
 
@@ -65,6 +68,13 @@ struct fdas_plan {
     uint32_t flags = 0;
     int fused_per_cu = 1;
     int topk_per_cu = 1;
+    int prec = 0;              // 0 float32, 1 binary16, 2 bfloat16
+    int mixed_per_cu = 1;
+    int eh = 0;                // template spectra scaled by 2^eh in 16-bit storage
+    uint32_t *d_H16 = nullptr; // [M][2048] packed 16-bit pairs, pass-A lane order
+    void *d_mat = nullptr;     // 16-bit DFT matrices of the inverse passes
+    void *d_stage = nullptr;   // scaled segment spectra of one call (16-bit plans)
+    hipEvent_t stage_free = nullptr;  // recorded after each call that used d_stage
     c32 *d_H = nullptr;        // [M][L], permuted frequency order per template
     c32 *d_tw = nullptr;       // [L]
     c32 *d_taps = nullptr;     // [M][kp], zero beyond tap_len
@@ -81,6 +91,10 @@ void free_plan(fdas_plan *p)
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_tap_len) (void)hipFree(p->d_tap_len);
+    if (p->d_H16) (void)hipFree(p->d_H16);
+    if (p->d_mat) (void)hipFree(p->d_mat);
+    if (p->d_stage) (void)hipFree(p->d_stage);
+    if (p->stage_free) (void)hipEventDestroy(p->stage_free);
     delete p;
 }
 
@@ -94,7 +108,7 @@ int check_io(const fdas_plan *plan, const void *d_in, int64_t n, const float *d_
         return fail(FDAS_EINVAL, "n=%lld outside [1, input_len=%lld]", (long long)n,
                     (long long)plan->input_len);
     if (ld_power < n) return fail(FDAS_EINVAL, "ld_power=%lld < n=%lld", (long long)ld_power, (long long)n);
-    if (((uintptr_t)d_in) % 8 != 0) return fail(FDAS_EINVAL, "d_in is not 8-byte aligned");
+    if (((uintptr_t)d_in) % (plan->prec ? 4 : 8) != 0) return fail(FDAS_EINVAL, "d_in is misaligned");
     if (((uintptr_t)d_power) % 4 != 0) return fail(FDAS_EINVAL, "d_power is not 4-byte aligned");
     return FDAS_OK;
 }
@@ -108,8 +122,12 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     g_last_error.clear();
     if (!out) return fail(FDAS_EINVAL, "out is NULL");
     *out = nullptr;
-    if ((flags & ~FDAS_TAPS_ON_DEVICE) != 0)
-        return fail(FDAS_EUNSUPPORTED, "unsupported flags 0x%x (only FDAS_FP32 storage is built)", flags);
+    if ((flags & ~(FDAS_TAPS_ON_DEVICE | FDAS_FP16 | FDAS_BF16)) != 0 ||
+        ((flags & FDAS_FP16) && (flags & FDAS_BF16)))
+        return fail(FDAS_EUNSUPPORTED, "unsupported flags 0x%x", flags);
+    const int prec = (flags & FDAS_FP16) ? 1 : (flags & FDAS_BF16) ? 2 : 0;
+    if (prec != 0 && seg_fft != 0 && seg_fft != 2048)
+        return fail(FDAS_EUNSUPPORTED, "16-bit plans are built for seg_fft = 2048 only");
     if (!taps) return fail(FDAS_EINVAL, "taps is NULL");
     if (M < 1) return fail(FDAS_EINVAL, "M=%d < 1", M);
     if (K_max < 1) return fail(FDAS_EINVAL, "K_max=%d < 1", K_max);
@@ -146,6 +164,7 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     p->kp = (K_max + 7) / 8 * 8;
     p->input_len = input_len;
     p->flags = flags;
+    p->prec = prec;
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
@@ -194,6 +213,32 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
 
     p->fused_per_cu = fdas::fused_blocks_per_cu(L);
     p->topk_per_cu = fdas::topk_blocks_per_cu(L);
+    if (prec != 0) {
+        // 16-bit spectra in the matrix-core lane order, scaled by 2^eh so the
+        // largest component is in (1/2, 1]
+        std::vector<c32> hf((size_t)M * L);
+        e = hipMemcpy(hf.data(), p->d_H, sizeof(c32) * hf.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { free_plan(p); return hip_fail(e, "reading template spectra"); }
+        float mx = 0.f;
+        for (const c32 &z : hf) mx = std::max(mx, std::max(std::fabs(z.re), std::fabs(z.im)));
+        int ex = 0;
+        if (mx > 0.f) std::frexp(mx, &ex);           // mx < 2^ex
+        p->eh = -ex;
+        const size_t bytes16 = sizeof(uint32_t) * (size_t)M * L;
+        const size_t stage = fdas::mixed_stage_bytes((input_len + p->V - 1) / p->V);
+        e = hipMalloc((void **)&p->d_H16, bytes16);
+        if (e == hipSuccess) e = hipMalloc(&p->d_mat, fdas::mixed_matrix_bytes());
+        if (e == hipSuccess) e = hipMalloc(&p->d_stage, stage);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->stage_free, hipEventDisableTiming);
+        if (e == hipSuccess) e = fdas::launch_mat_table(prec == 2, p->d_mat, st);
+        if (e == hipSuccess)
+            e = fdas::launch_tspec_mix(p->d_taps, p->d_tap_len, p->kp, M, std::ldexp(1.f, p->eh), prec == 2,
+                                       p->d_H16, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { free_plan(p); return hip_fail(e, "building 16-bit template spectra"); }
+        p->resident_bytes += (int64_t)(bytes16 + fdas::mixed_matrix_bytes() + stage);
+        p->mixed_per_cu = fdas::mixed_blocks_per_cu(prec == 2);
+    }
     *out = p;
     return FDAS_OK;
 }
@@ -214,6 +259,33 @@ FDAS_API int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, f
     g_last_error.clear();
     int rc = check_io(plan, d_in, n, d_power, ld_power);
     if (rc != FDAS_OK) return rc;
+    if (plan->prec != 0) {
+        fdas::MixedArgs m;
+        m.x = d_in;
+        m.n = n;
+        m.H16 = plan->d_H16;
+        m.mat = plan->d_mat;
+        m.twL = plan->d_tw;
+        m.M = plan->M;
+        m.D = plan->D;
+        m.V = plan->V;
+        m.eh = plan->eh;
+        m.bf = plan->prec == 2;
+        m.segments = (n + plan->V - 1) / plan->V;
+        m.items = m.segments * plan->M;
+        m.grid = std::max<int64_t>(1, std::min<int64_t>(m.items, (int64_t)plan->mixed_per_cu * std::max(1, plan->num_cu)));
+        m.stage = plan->d_stage;
+        m.P = d_power;
+        m.ld = ld_power;
+        // calls on one plan share its staging buffer: each call waits for the
+        // previous one (on whatever stream it ran) before writing it
+        hipStream_t st = (hipStream_t)hip_stream;
+        hipError_t e = hipStreamWaitEvent(st, plan->stage_free, 0);
+        if (e == hipSuccess) e = fdas::launch_mixed(m, st);
+        if (e == hipSuccess) e = hipEventRecord(plan->stage_free, st);
+        if (e != hipSuccess) return hip_fail(e, "launching the 16-bit FDFIR kernels");
+        return FDAS_OK;
+    }
     fdas::FusedArgs a;
     a.x = d_in;
     a.n = n;
@@ -238,6 +310,7 @@ FDAS_API int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, floa
     g_last_error.clear();
     int rc = check_io(plan, d_in, n, d_power, ld_power);
     if (rc != FDAS_OK) return rc;
+    if (plan->prec != 0) return fail(FDAS_EUNSUPPORTED, "fdas_tdfir takes float32 plans only");
     fdas::TdArgs a;
     a.x = d_in;
     a.n = n;
@@ -334,6 +407,7 @@ FDAS_API int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_i
     BatchShape sh;
     int rc = batch_shape(plan, n, count, topk, sh);
     if (rc != FDAS_OK) return rc;
+    if (plan->prec != 0) return fail(FDAS_EUNSUPPORTED, "fdas_convolve_batched takes float32 plans only");
     if (!d_in) return fail(FDAS_EINVAL, "d_in is NULL");
     if (!d_out || ((uintptr_t)d_out) % 4) return fail(FDAS_EINVAL, "d_out is NULL or not 4-byte aligned");
     if (!d_workspace || ((uintptr_t)d_workspace) % kAlign)
@@ -370,6 +444,7 @@ FDAS_API int fdas_segment_fft(const fdas_plan *plan, const void *d_in, void *d_o
 {
     g_last_error.clear();
     if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    if (plan->prec != 0) return fail(FDAS_EUNSUPPORTED, "fdas_segment_fft takes float32 plans only");
     if (!d_in || !d_out) return fail(FDAS_EINVAL, "NULL buffer");
     if (count < 1 || count > 0x7fffffffLL) return fail(FDAS_EINVAL, "count=%lld out of range", (long long)count);
     if (direction != -1 && direction != 1) return fail(FDAS_EINVAL, "direction=%d not -1 or +1", direction);
@@ -413,7 +488,7 @@ FDAS_API int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out)
     out->resident_bytes = plan->resident_bytes;
     out->threads_per_fft = plan->L / 16;
     out->fused_grid = (int32_t)fused_grid(plan, out->num_segments * plan->M);
-    out->variant = kVariantFusedPersistent;
+    out->variant = plan->prec == 1 ? kVariantMixedFp16 : plan->prec == 2 ? kVariantMixedBf16 : kVariantFusedPersistent;
     out->device = plan->device;
     return FDAS_OK;
 }
@@ -447,6 +522,8 @@ FDAS_API const char *fdas_variant_name(int32_t variant)
 {
     switch (variant) {
     case kVariantFusedPersistent: return "fused-ols-persistent-fp32";
+    case kVariantMixedFp16: return "fused-ols-mfma-fp16";
+    case kVariantMixedBf16: return "fused-ols-mfma-bf16";
     default: return "unknown";
     }
 }

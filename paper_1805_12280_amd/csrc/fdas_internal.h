@@ -60,6 +60,21 @@ struct TopkArgs {
     void *out;            // fdas_cand [count][K]
 };
 
+struct MixedArgs {
+    const void *x;        // 16-bit complex [n]
+    int64_t n;
+    const void *H16;      // 16-bit complex [M][2048], pass-A lane order
+    const void *mat;      // DFT matrices of the three passes (mixed_matrix_bytes())
+    const c32 *twL;
+    int M, D, V, eh;
+    bool bf;
+    int64_t items, grid;
+    int64_t segments;     // ceil(n / V)
+    void *stage;          // mixed_stage_bytes(segments): scaled spectra and power scales
+    float *P;
+    int64_t ld;
+};
+
 hipError_t launch_twiddles(c32 *twL, int L, hipStream_t st);
 hipError_t launch_tspec(const c32 *taps, const int *tap_len, int kp, int M, int L, c32 *H,
                         hipStream_t st);
@@ -69,6 +84,13 @@ hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int 
                          hipStream_t st);
 size_t tdfir_lds_bytes(int kp);
 int topk_blocks_per_cu(int L);
+hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
+                            uint32_t *H16, hipStream_t st);
+int mixed_blocks_per_cu(bool bf);
+size_t mixed_matrix_bytes();
+size_t mixed_stage_bytes(int64_t segments);
+hipError_t launch_mat_table(bool bf, void *tab, hipStream_t st);
+hipError_t launch_mixed(const MixedArgs &a, hipStream_t st);
 hipError_t launch_topk(const TopkArgs &a, hipStream_t st);
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
 

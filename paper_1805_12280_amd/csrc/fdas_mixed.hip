@@ -1,0 +1,425 @@
+// fdas_mixed.hip -- the overlap-save hot path with 16-bit storage and the
+// inverse segment transforms on the matrix cores (FP16 or BF16 operands,
+// FP32 accumulation).  L = 2048.
+//
+// Per segment (once, VALU, float32): gather the 16-bit input, forward FFT
+// (seg_fft.h), redistribute the spectrum X into the lanes that feed pass A
+// (mixed_fft.h), and pick a power-of-two scale sigma from max |X| so the
+// 16-bit operands stay well inside their range.  Per (segment, template):
+// Z = sigma X H (FP32) rounded once to 16 bits, passes A, B, C as matrix
+// products, |y|^2 unscaled exactly by the powers of two, non-temporal store.
+#include "fdas_internal.h"
+#include "mixed_fft.h"
+#include "seg_fft.h"
+
+namespace fdas {
+
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Storage type: complex value as a pair of 16-bit numbers in one 32-bit word.
+template <bool BF> struct Half;
+
+template <> struct Half<false> {   // IEEE binary16
+    __device__ static uint32_t pack(float re, float im)
+    {
+        h2v v = {(_Float16)re, (_Float16)im};   // round to nearest even
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    __device__ static c32 unpack(uint32_t w)
+    {
+        const h2v v = __builtin_bit_cast(h2v, w);
+        return mk((float)v.x, (float)v.y);
+    }
+    __device__ static f4v mma16(uint2 a, uint2 b, f4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4v, a), __builtin_bit_cast(h4v, b), c, 0, 0, 0);
+    }
+    __device__ static f4v mma32(uint4 a, uint4 b, f4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+    }
+};
+
+template <> struct Half<true> {    // bfloat16
+    __device__ static uint32_t pack(float re, float im)
+    {
+        b2v v = {(__bf16)re, (__bf16)im};       // round to nearest even
+        return __builtin_bit_cast(uint32_t, v);
+    }
+    __device__ static c32 unpack(uint32_t w)
+    {
+        return mk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+    }
+    __device__ static f4v mma16(uint2 a, uint2 b, f4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0, 0, 0);
+    }
+    __device__ static f4v mma32(uint4 a, uint4 b, f4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0, 0);
+    }
+};
+
+// One real matrix entry of exp(2 pi i turns) for interleaved rows/columns.
+__device__ __forceinline__ float wentry(int row, int k, double turns)
+{
+    double s, c;
+    sincospi(2.0 * turns, &s, &c);
+    switch (mix::entry_sel(row, k)) {
+    case 0: return (float)c;
+    case 1: return (float)-s;
+    case 2: return (float)s;
+    default: return (float)c;
+    }
+}
+
+template <bool BF> __device__ __forceinline__ uint32_t pack_pair_scalar(float a, float b) { return Half<BF>::pack(a, b); }
+
+// ---------------------------------------------------------------------------
+// template spectra in the lane layout of pass A, 16-bit, scaled by 2^eh
+// ---------------------------------------------------------------------------
+
+template <bool BF>
+__global__ void tspec_mix_kernel(const c32 *__restrict__ taps, const int *__restrict__ tap_len, int kp, int M,
+                                 float scale, uint32_t *__restrict__ H16)
+{
+    using namespace mix;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * L) return;
+    const int t = (int)(idx / L);
+    const int rem = (int)(idx - (int64_t)t * L);      // (w * 64 + l) * 16 + v
+    const int v = rem & 15, wl = rem >> 4, w = wl >> 6, l = wl & 63;
+    const int q = zq(w, l, v);
+    const c32 *h = taps + (int64_t)t * kp;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < tap_len[t]; ++k) {
+        const int r = (int)(((int64_t)q * k) & (L - 1));
+        double s, c;
+        sincospi(-2.0 * (double)r / (double)L, &s, &c);
+        const double hr = h[k].re, hi = h[k].im;
+        re += hr * c - hi * s;
+        im += hr * s + hi * c;
+    }
+    H16[idx] = Half<BF>::pack((float)(re / L * scale), (float)(im / L * scale));
+}
+
+// ---------------------------------------------------------------------------
+// fused kernel
+// ---------------------------------------------------------------------------
+
+// The DFT matrices in operand lane order, 16-bit:
+//   MA[r * 64 + lane]  pass A for column set r (W128^(p r) folded in): 4 values (uint2)
+//   MD[h * 64 + lane]  DFT16 of passes B and C, output half h: 8 values (uint4)
+constexpr int MAT_A_UINT2 = 16 * 64;
+constexpr int MAT_D = MAT_A_UINT2 / 2;         // in uint4 units
+constexpr int MAT_UINT4 = MAT_D + 2 * 64;
+constexpr size_t MAT_BYTES = MAT_UINT4 * sizeof(uint4);
+
+template <bool BF>
+__global__ void mat_table_kernel(uint4 *__restrict__ tab)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = idx & 63, i = l & 15, g = l >> 4;
+    if (idx < MAT_A_UINT2) {
+        const int r = idx >> 6;
+        float e4[4];
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * g + e;
+            e4[e] = wentry(i, k, mix::turns_A(r, i >> 1, k >> 1));
+        }
+        reinterpret_cast<uint2 *>(tab)[idx] = make_uint2(Half<BF>::pack(e4[0], e4[1]), Half<BF>::pack(e4[2], e4[3]));
+    } else if (idx < MAT_A_UINT2 + 2 * 64) {
+        const int h = (idx - MAT_A_UINT2) >> 6, out = 8 * h + (i >> 1);
+        float e8[8];
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+            e8[e] = wentry(i, k, mix::turns_D16(out, k >> 1));
+        }
+        tab[MAT_D + h * 64 + l] = make_uint4(Half<BF>::pack(e8[0], e8[1]), Half<BF>::pack(e8[2], e8[3]),
+                                             Half<BF>::pack(e8[4], e8[5]), Half<BF>::pack(e8[6], e8[7]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per segment: forward FFT (float32) and the power-of-two scale
+// ---------------------------------------------------------------------------
+
+// Xs[s][v / 2][tau] holds, as float4 (two complex values), sigma_s X_s at the
+// frequencies zq(w, l, v) and zq(w, l, v + 1) that work-item tau = 64 w + l
+// feeds to pass A; ps[s] = 2^-2(e_s + eh) undoes both scalings of |y|^2.
+template <bool BF>
+__global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restrict__ x16, int64_t n,
+                                                        const c32 *__restrict__ twL, int D, int V, int eh,
+                                                        float4 *__restrict__ Xs, float *__restrict__ ps)
+{
+    using SG = Seg<2048>;
+    using HF = Half<BF>;
+    constexpr int L = mix::L, T = mix::T;
+    __shared__ c32 lds[2 * SG::LDS_ELEMS];
+    __shared__ float s_max[2];
+    c32 *bufA = lds, *bufC = lds + SG::LDS_ELEMS;
+    const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
+    const int64_t s = blockIdx.x, base = s * V - D;
+
+    c32 v[16];
+    {
+        const uint32_t *xs = x16 + base;
+        const int lo = (int)max<int64_t>(0, -base), hi = (int)min<int64_t>(L, n - base);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = tau + T * m;
+            v[m] = (j >= lo && j < hi) ? HF::unpack(xs[j]) : mk(0.f, 0.f);
+        }
+    }
+    {
+        c32 tw0[16], tw1[16];
+        SG::twiddles(tau, twL, tw0, tw1);
+        SG::fwd0(tau, v, tw0);
+        SG::put_a(tau, v, bufA);
+        __syncthreads();
+        SG::fwd1(tau, v, bufA, tw1);
+    }
+    SG::put_c(tau, v, bufC);
+    __syncthreads();
+    SG::fwd2(tau, v, bufC);
+    __syncthreads();
+    // redistribute X to the pass-A lanes through LDS, rows of 16 frequencies
+    // padded to 17: slot(q) = q + q / 16.  Register e holds
+    // q = k1 + 16 (2 p + e / 8) + 256 (e % 8) (R2 = 8, G = 2), so
+    // slot = (k1 + 34 p) + 17 (e / 8) + 272 (e % 8).
+    float mx = 0.f;
+    {
+        c32 *dst = lds + SG::k1_of(tau) + 34 * SG::p_of(tau);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            dst[17 * (e >> 3) + 272 * (e & 7)] = v[e];
+            mx = fmaxf(mx, fmaxf(fabsf(v[e].re), fabsf(v[e].im)));
+        }
+    }
+    // workgroup max of the component magnitudes
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (l == 0) s_max[w] = mx;
+    __syncthreads();
+    mx = fmaxf(s_max[0], s_max[1]);
+    // sigma = 2^es with 2 sigma max|X| max|H16| <= 16 (max|H16| <= 1)
+    int es = 0;
+    if (mx > 0.f) {
+        int ex;
+        frexpf(2.f * mx, &ex);             // 2 mx < 2^ex
+        es = 4 - ex;
+    }
+    const float sigma = ldexpf(1.f, es);
+    if (tau == 0) ps[s] = ldexpf(1.f, -2 * (es + eh));
+    // lane (w, l) takes q = zq(w, l, v): slot = (col + 136 w + 544 g)
+    // + 17 (v / 2) + 272 (v % 2)
+    const c32 *src = lds + col + 136 * w + 544 * g;
+    float4 *out = Xs + s * (L / 2) + tau;
+#pragma unroll
+    for (int vp = 0; vp < 8; ++vp) {
+        const c32 z0 = src[17 * vp], z1 = src[17 * vp + 272];
+        out[vp * T] = make_float4(z0.re * sigma, z0.im * sigma, z1.re * sigma, z1.im * sigma);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per (segment, template): Z = X H, inverse on the matrix cores, power
+// ---------------------------------------------------------------------------
+
+template <bool BF>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_kernel(
+    const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const uint32_t *__restrict__ H16,
+    const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int64_t items,
+    float *__restrict__ P, int64_t ld)
+{
+    using HF = Half<BF>;
+    constexpr int L = mix::L, T = mix::T, BJ = mix::BJ;
+    __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
+    __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
+
+    const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
+    // per-lane bases of the exchanges (the per-group offsets below are
+    // compile-time constants)
+    uint32_t *const ccw = cc + mix::cc_word(2 * g, col, 8 * w);       // pass A: c[2g + c][col][8w + 4a ..]
+    const uint32_t *const ccr = cc + mix::cc_word(4 * w, col, 4 * g); // pass B: c[4w + gam][col][4g ..]
+    uint32_t *const bbw = bb + mix::bb_word(4 * w + 16 * g, col);     // pass B: b[col][j = 4w + gam + 8 q']
+    const uint32_t *const bbr = bb + mix::bb_word(64 * w + col, 4 * g); // pass C: b[4g ..][16 (4w + gam) + col]
+    const int nbase = 64 * w + col + 256 * g;
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
+    if (u0 >= u1) return;
+
+    // DFT matrices (16-bit) and the pass-B output twiddles (FP32), per lane
+    uint2 aA[8];
+#pragma unroll
+    for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
+    const uint4 aD[2] = {mat[MAT_D + l], mat[MAT_D + 64 + l]};
+    c32 twc[4][2][2];
+#pragma unroll
+    for (int gam = 0; gam < 4; ++gam)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
+                const c32 f = twL[(j * col) & (L - 1)];        // exp(-2 pi i j k1 / L)
+                twc[gam][h][i] = mk(f.re, -f.im);
+            }
+
+    int64_t s = u0 / M;
+    int t = (int)(u0 - s * M);
+    uint4 Hn[4];                       // 16 packed values of this lane, template t
+    {
+        const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)t * L) + tau * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
+    }
+    c32 X[16];                         // sigma-scaled spectrum at zq(w, l, v)
+    float pscale = 1.f;
+    int64_t cur = -1;
+    for (int64_t u = u0; u < u1; ++u) {
+        const int64_t base = s * V - D;
+        if (s != cur) {
+            cur = s;
+            const float4 *src = Xs + s * (L / 2) + tau;
+#pragma unroll
+            for (int vp = 0; vp < 8; ++vp) {
+                const float4 f = src[vp * T];
+                X[2 * vp] = mk(f.x, f.y);
+                X[2 * vp + 1] = mk(f.z, f.w);
+            }
+            pscale = ps[s];
+        }
+        // ---- pass A: Z = X H rounded once, radix 8 over s, twiddle folded ----
+        uint32_t pa[2][8];             // c[2g + c][col][8w + gam]
+#pragma unroll
+        for (int gam = 0; gam < 8; ++gam) {
+            const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
+            const c32 z0 = mul(X[2 * gam], HF::unpack(hw0));
+            const c32 z1 = mul(X[2 * gam + 1], HF::unpack(hw1));
+            const uint2 bop = make_uint2(HF::pack(z0.re, z0.im), HF::pack(z1.re, z1.im));
+            const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
+            pa[0][gam] = HF::pack(d[0], d[1]);
+            pa[1][gam] = HF::pack(d[2], d[3]);
+        }
+        // next item's template spectra, in flight during this transform
+        const int tn = (t + 1 == M) ? 0 : t + 1;
+        {
+            const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)tn * L) + tau * 4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
+        }
+        // the previous item's pass C has finished reading bb, and its pass B
+        // reading cc, before any work-item passes the barrier after pass B
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                *reinterpret_cast<uint4 *>(ccw + 16 * c + 4 * a) =
+                    make_uint4(pa[c][4 * a], pa[c][4 * a + 1], pa[c][4 * a + 2], pa[c][4 * a + 3]);
+        __syncthreads();
+        // ---- pass B: radix 16 over r, then the twiddle W2048^(j k1) ----
+        uint32_t pb[2][2][4];          // [h][i][gam]
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam) {
+            const uint4 bop = *reinterpret_cast<const uint4 *>(ccr + 16 * gam);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const c32 y = mul(mk(d[2 * i], d[2 * i + 1]), twc[gam][h][i]);
+                    pb[h][i][gam] = HF::pack(y.re, y.im);
+                }
+            }
+        }
+        // b[col][j], j = 4w + gam + 8 (8h + 2g + i): four consecutive j per store
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                *reinterpret_cast<uint4 *>(bbw + (16 * h + 2 * i) * BJ) =
+                    make_uint4(pb[h][i][0], pb[h][i][1], pb[h][i][2], pb[h][i][3]);
+        __syncthreads();
+        // ---- pass C: radix 16 over k1, power, store ----
+        float *Pt = P + (int64_t)t * ld + base;
+        const int hi = (int)min<int64_t>(L, n - base);
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam) {
+            const uint32_t *src = bbr + 4 * gam * BJ;     // j = 16 (4w + gam) + col
+            const uint4 bop = make_uint4(src[0], src[4], src[8], src[12]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    // output n = j + 128 m, m = 8 h + 2 g + i
+                    const int nn = nbase + 16 * gam + 1024 * h + 128 * i;
+                    if (nn >= D && nn < hi)
+                        __builtin_nontemporal_store((d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale, Pt + nn);
+                }
+            }
+        }
+        t = tn;
+        if (t == 0) ++s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+size_t mixed_matrix_bytes() { return MAT_BYTES; }
+
+hipError_t launch_mat_table(bool bf, void *tab, hipStream_t st)
+{
+    const dim3 grid((MAT_A_UINT2 + 2 * 64 + 255) / 256), blk(256);
+    if (bf) hipLaunchKernelGGL(mat_table_kernel<true>, grid, blk, 0, st, (uint4 *)tab);
+    else hipLaunchKernelGGL(mat_table_kernel<false>, grid, blk, 0, st, (uint4 *)tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
+                            uint32_t *H16, hipStream_t st)
+{
+    const int64_t total = (int64_t)M * mix::L;
+    dim3 grid((unsigned)((total + 255) / 256)), blk(256);
+    if (bf) hipLaunchKernelGGL(tspec_mix_kernel<true>, grid, blk, 0, st, taps, tap_len, kp, M, scale, H16);
+    else hipLaunchKernelGGL(tspec_mix_kernel<false>, grid, blk, 0, st, taps, tap_len, kp, M, scale, H16);
+    return hipGetLastError();
+}
+
+int mixed_blocks_per_cu(bool bf)
+{
+    int nb = 0;
+    hipError_t e = bf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel<true>, 128, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel<false>, 128, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+size_t mixed_stage_bytes(int64_t segments) { return (size_t)segments * (mix::L * sizeof(c32) + sizeof(float)); }
+
+hipError_t launch_mixed(const MixedArgs &a, hipStream_t st)
+{
+    // stage: [segments][L] complex float32, then [segments] float
+    float4 *Xs = (float4 *)a.stage;
+    float *ps = (float *)((char *)a.stage + (size_t)a.segments * mix::L * sizeof(c32));
+    const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
+    if (a.bf) {
+        hipLaunchKernelGGL(mixed_fwd_kernel<true>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,
+                           a.eh, Xs, ps);
+        hipLaunchKernelGGL(fdfir_mixed_kernel<true>, gi, blk, 0, st, Xs, ps, a.n, (const uint32_t *)a.H16, a.twL,
+                           (const uint4 *)a.mat, a.M, a.D, a.V, a.items, a.P, a.ld);
+    } else {
+        hipLaunchKernelGGL(mixed_fwd_kernel<false>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,
+                           a.eh, Xs, ps);
+        hipLaunchKernelGGL(fdfir_mixed_kernel<false>, gi, blk, 0, st, Xs, ps, a.n, (const uint32_t *)a.H16, a.twL,
+                           (const uint4 *)a.mat, a.M, a.D, a.V, a.items, a.P, a.ld);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fdas

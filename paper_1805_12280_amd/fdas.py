@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(_PKG, "libfdas.so")
 FDAS_OK, FDAS_EINVAL, FDAS_ENOMEM, FDAS_EHIP, FDAS_EUNSUPPORTED = 0, 1, 2, 3, 4
 FDAS_FP32 = 0
 FDAS_TAPS_ON_DEVICE = 1
+FDAS_FP16 = 2
+FDAS_BF16 = 4
+PRECISIONS = {"fp32": FDAS_FP32, "fp16": FDAS_FP16, "bf16": FDAS_BF16}
 
 MAX_BATCH = 128
 MAX_TOPK = 32
@@ -116,15 +119,19 @@ class Plan:
     tap_len:  int32 [M] or None (all K_max)
     input_len: largest spectrum length that will be filtered
     seg_fft:  segment transform length L in {1024, 2048, 4096}
+    precision: "fp32", or "fp16" / "bf16" for the mixed plans (16-bit input
+               and template spectra, matrix-core inverse transforms, float32
+               accumulation and power; L = 2048, convolve() only)
     """
 
     def __init__(self, taps, tap_len=None, input_len: int = 1 << 22, seg_fft: int = 2048,
                  precision: str = "fp32", stream=None):
         import torch
-        if precision != "fp32":
-            raise FdasError(FDAS_EUNSUPPORTED, f"precision {precision!r} is not built")
+        if precision not in PRECISIONS:
+            raise FdasError(FDAS_EINVAL, f"precision {precision!r}: one of {sorted(PRECISIONS)}")
         lib = load_library()
-        flags = FDAS_FP32
+        flags = PRECISIONS[precision]
+        self.precision = precision
         keep = []
         if isinstance(taps, torch.Tensor) and taps.is_cuda:
             taps_t = taps.to(torch.complex64).contiguous()
@@ -179,12 +186,23 @@ class Plan:
         return self._lib.fdas_variant_name(self.info.variant).decode()
 
     # -- calls --------------------------------------------------------------
+    def input_dtype(self):
+        """torch dtype of one real component of the input spectrum."""
+        import torch
+        return {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[self.precision]
+
     def _io(self, x, out):
         import torch
-        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64):
-            raise FdasError(FDAS_EINVAL, "x must be a CUDA complex64 tensor")
-        if x.dim() != 1 or not x.is_contiguous():
-            raise FdasError(FDAS_EINVAL, "x must be 1-D and contiguous")
+        if self.precision == "fp32":
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64):
+                raise FdasError(FDAS_EINVAL, "x must be a CUDA complex64 tensor")
+            if x.dim() != 1 or not x.is_contiguous():
+                raise FdasError(FDAS_EINVAL, "x must be 1-D and contiguous")
+        else:
+            want = self.input_dtype()
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 2
+                    and x.shape[1] == 2 and x.is_contiguous()):
+                raise FdasError(FDAS_EINVAL, f"x must be a contiguous CUDA {want} tensor [n, 2] (re, im)")
         n = x.shape[0]
         if out is None:
             out = torch.empty((self.num_templates, n), dtype=torch.float32, device=x.device)
