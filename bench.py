@@ -6,8 +6,10 @@ transform L = 2048, writing the 85 x 2^22 float32 power plane.  The input
 and the output plane are resident in HBM before timing starts.
 
 Prints one JSON line (rank 0).  Extra legs: the direct TDFIR baseline on the
-same workload, and the FP64 CPU oracle timed on a bounded sample of the same
-workload (which also gives a parity figure for the sampled rows).
+same workload, the 16-bit (FP16/BF16) plans on the same workload, the batched
+DM-trial form, the served loop, paper-shaped sweeps, and the FP64 CPU oracle
+timed on a bounded sample of the same workload (which also gives a parity
+figure for the sampled rows).
 """
 from __future__ import annotations
 
@@ -220,6 +222,34 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
     return out
 
 
+def mixed_leg(torch, fdas, w, x32, P32, steps, warmup, fp32_ms):
+    """The 16-bit plans (FP16 and BF16 storage, matrix-core inverse FFT) on
+    the same 85 x 2^22 workload: time per call, speedup over the float32
+    path, and the peak-normalised deviation of the whole plane from the
+    float32 path's plane P32 (whose own error against the FP64 oracle is
+    below 1e-4; the 16-bit plans' parity with the oracle is in the tests)."""
+    m, n = w.bank.num_templates, w.n
+    out = torch.empty((m, n), dtype=torch.float32, device=x32.device)
+    peak = P32.max()
+    res = {}
+    for prec in ("fp16", "bf16"):
+        plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=2048, precision=prec)
+        xh = torch.view_as_real(x32).to(plan.input_dtype()).contiguous()
+        ms = time_calls(torch, lambda: plan.convolve(xh, out=out), steps, warmup)
+        dev = float(((out - P32).abs().max() / peak).item())
+        rr = float((torch.linalg.vector_norm((out - P32).flatten().double())
+                    / torch.linalg.vector_norm(P32.flatten().double())).item())
+        res[prec] = {"ms_per_step": ms, "value": m * n / (ms * 1e-3), "unit": "template-samples/s",
+                     "speedup_vs_fp32": fp32_ms / ms, "variant": plan.variant,
+                     "resident_bytes": int(plan.info.resident_bytes),
+                     "max_dev_vs_fp32_plane": dev, "rrmse_vs_fp32_plane": rr}
+        log(f"{prec}: {ms:.4f} ms/step ({fp32_ms / ms:.2f}x fp32), peak-normalised deviation "
+            f"from the float32 plane {dev:.2e}")
+        plan.close()
+    del out
+    return res
+
+
 def sweeps_leg(torch, fdas):
     """The paper's experiment shapes on this GPU.
     fig8: M = 84 filters of 421 taps, inputs 2^18..2^22, FDFIR + power; the
@@ -268,6 +298,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-sweeps", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling PMC byte counters)")
@@ -357,6 +388,10 @@ def main():
         log(f"fdas_tdfir: {td_ms:.3f} ms/step")
         plan.convolve(x, out=out)          # leave the FDFIR plane in `out`
         torch.cuda.synchronize()
+
+    if not args.no_mixed:
+        plan.convolve(x, out=out)
+        result["mixed"] = mixed_leg(torch, fdas, w, x, out, args.steps, args.warmup, ms)
 
     if not args.no_batch:
         result["batched"] = batched_leg(torch, fdas, max(3, args.steps // 4), 2)

@@ -28,13 +28,19 @@ template <bool BF> struct Half;
 template <> struct Half<false> {   // IEEE binary16
     __device__ static uint32_t pack(float re, float im)
     {
+        // opaque to the compiler, so the arithmetic that produced re and im
+        // stays in float32 instead of being fused into half-writing
+        // mixed-precision FMAs (a slower, serialised form here)
+        __asm__("" : "+v"(re), "+v"(im));
         h2v v = {(_Float16)re, (_Float16)im};   // round to nearest even
         return __builtin_bit_cast(uint32_t, v);
     }
     __device__ static c32 unpack(uint32_t w)
     {
         const h2v v = __builtin_bit_cast(h2v, w);
-        return mk((float)v.x, (float)v.y);
+        float re = (float)v.x, im = (float)v.y;
+        __asm__("" : "+v"(re), "+v"(im));      // plain conversions, then float32 arithmetic
+        return mk(re, im);
     }
     __device__ static f4v mma16(uint2 a, uint2 b, f4v c)
     {
@@ -231,6 +237,14 @@ __global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restri
 // per (segment, template): Z = X H, inverse on the matrix cores, power
 // ---------------------------------------------------------------------------
 
+// Buffer resource word 3 of the gfx9 family (32-bit data format; offsets are
+// range-checked against num_records and out-of-range stores are dropped),
+// and the cache-policy bit of a streaming (non-temporal) store.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt at their maxima (gfx9 encoding)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 template <bool BF>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_kernel(
     const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const uint32_t *__restrict__ H16,
@@ -241,6 +255,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     constexpr int L = mix::L, T = mix::T, BJ = mix::BJ;
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
+    // per-wave transpose of the powers: a wave's pass C yields outputs
+    // n = 64 w + j' + 128 m (j' < 64, m < 16) with 16 consecutive j' per lane
+    // group; staged as [m][j'] (row pitch OT_ROW) they are stored back as 16
+    // rows of 64 consecutive floats
+    constexpr int OT_ROW = 72;      // 64 + 8: the four lane groups (rows 2 apart) hit distinct banks
+    __shared__ float ot[2][16 * OT_ROW];
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
     // per-lane bases of the exchanges (the per-group offsets below are
@@ -249,7 +269,6 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     const uint32_t *const ccr = cc + mix::cc_word(4 * w, col, 4 * g); // pass B: c[4w + gam][col][4g ..]
     uint32_t *const bbw = bb + mix::bb_word(4 * w + 16 * g, col);     // pass B: b[col][j = 4w + gam + 8 q']
     const uint32_t *const bbr = bb + mix::bb_word(64 * w + col, 4 * g); // pass C: b[4g ..][16 (4w + gam) + col]
-    const int nbase = 64 * w + col + 256 * g;
     const int64_t nb = gridDim.x, b = blockIdx.x;
     const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
     if (u0 >= u1) return;
@@ -271,59 +290,73 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
                 twc[gam][h][i] = mk(f.re, -f.im);
             }
 
-    int64_t s = u0 / M;
+    // Items run as a software pipeline over the two exchange buffers: after
+    // pass B of item u (cc -> bb) and a barrier, pass C of item u (reads bb)
+    // and pass A of item u + 1 (writes cc) run interleaved in one phase, so
+    // the matrix products of one overlap the vector work of the other.
+    int64_t s = u0 / M;                // segment and template of item u
     int t = (int)(u0 - s * M);
-    uint4 Hn[4];                       // 16 packed values of this lane, template t
-    {
-        const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)t * L) + tau * 4;
+    int64_t sa = s;                    // segment and template of the pass-A item
+    int ta = t;
+    uint4 Hn[4];                       // template spectra of the pass-A item
+    auto load_h = [&](int tt) {
+        const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)tt * L) + tau * 4;
 #pragma unroll
         for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
-    }
-    c32 X[16];                         // sigma-scaled spectrum at zq(w, l, v)
-    float pscale = 1.f;
-    int64_t cur = -1;
-    for (int64_t u = u0; u < u1; ++u) {
-        const int64_t base = s * V - D;
-        if (s != cur) {
-            cur = s;
-            const float4 *src = Xs + s * (L / 2) + tau;
+    };
+    c32 X[16];                         // sigma-scaled spectrum of segment sa at zq(w, l, v)
+    auto load_x = [&](int64_t ss) {
+        const float4 *src = Xs + ss * (L / 2) + tau;
 #pragma unroll
-            for (int vp = 0; vp < 8; ++vp) {
-                const float4 f = src[vp * T];
-                X[2 * vp] = mk(f.x, f.y);
-                X[2 * vp + 1] = mk(f.z, f.w);
-            }
-            pscale = ps[s];
+        for (int vp = 0; vp < 8; ++vp) {
+            const float4 f = src[vp * T];
+            X[2 * vp] = mk(f.x, f.y);
+            X[2 * vp + 1] = mk(f.z, f.w);
         }
-        // ---- pass A: Z = X H rounded once, radix 8 over s, twiddle folded ----
-        uint32_t pa[2][8];             // c[2g + c][col][8w + gam]
-#pragma unroll
-        for (int gam = 0; gam < 8; ++gam) {
-            const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
-            const c32 z0 = mul(X[2 * gam], HF::unpack(hw0));
-            const c32 z1 = mul(X[2 * gam + 1], HF::unpack(hw1));
-            const uint2 bop = make_uint2(HF::pack(z0.re, z0.im), HF::pack(z1.re, z1.im));
-            const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
-            pa[0][gam] = HF::pack(d[0], d[1]);
-            pa[1][gam] = HF::pack(d[2], d[3]);
-        }
-        // next item's template spectra, in flight during this transform
-        const int tn = (t + 1 == M) ? 0 : t + 1;
-        {
-            const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)tn * L) + tau * 4;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
-        }
-        // the previous item's pass C has finished reading bb, and its pass B
-        // reading cc, before any work-item passes the barrier after pass B
+    };
+    // pass A, column set r = 8w + gam: Z = X H rounded once, radix 8 over s
+    // (twiddle folded into the matrix); returns c[2g + c][col][r] packed
+    auto pass_a = [&](int gam, uint32_t &c0, uint32_t &c1) {
+        const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
+        const c32 z0 = mul(X[2 * gam], HF::unpack(hw0));
+        const c32 z1 = mul(X[2 * gam + 1], HF::unpack(hw1));
+        const uint2 bop = make_uint2(HF::pack(z0.re, z0.im), HF::pack(z1.re, z1.im));
+        const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
+        c0 = HF::pack(d[0], d[1]);
+        c1 = HF::pack(d[2], d[3]);
+    };
+    auto store_a = [&](const uint32_t (&pa)[2][8]) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int a = 0; a < 2; ++a)
                 *reinterpret_cast<uint4 *>(ccw + 16 * c + 4 * a) =
                     make_uint4(pa[c][4 * a], pa[c][4 * a + 1], pa[c][4 * a + 2], pa[c][4 * a + 3]);
-        __syncthreads();
-        // ---- pass B: radix 16 over r, then the twiddle W2048^(j k1) ----
+    };
+    // advance the pass-A item; its template spectra are in flight from here on
+    auto next_a = [&]() {
+        if (++ta == M) { ta = 0; ++sa; }
+        load_h(ta);
+    };
+
+    load_h(ta);
+    load_x(sa);
+    float pscale = ps[s];              // 2^-2(e_s + eh) of the pass-A segment
+    {
+        uint32_t pa[2][8];
+#pragma unroll
+        for (int gam = 0; gam < 8; ++gam) pass_a(gam, pa[0][gam], pa[1][gam]);
+        next_a();
+        store_a(pa);
+    }
+    // Drain the prologue's loads here (matrices, twiddles, first spectra):
+    // a load still outstanding at the loop entry would otherwise leave a
+    // memory-counter wait inside the loop, which on every item would also
+    // wait for the previous item's power stores.
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    for (int64_t u = u0; u < u1; ++u) {
+        // ---- pass B of item u: radix 16 over r, then the twiddle W2048^(j k1) ----
         uint32_t pb[2][2][4];          // [h][i][gam]
 #pragma unroll
         for (int gam = 0; gam < 4; ++gam) {
@@ -345,28 +378,54 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
             for (int i = 0; i < 2; ++i)
                 *reinterpret_cast<uint4 *>(bbw + (16 * h + 2 * i) * BJ) =
                     make_uint4(pb[h][i][0], pb[h][i][1], pb[h][i][2], pb[h][i][3]);
+        // the pass-A item u + 1 may start a new segment (past the last item
+        // pass A runs on stale data and its result is never read)
+        const float pscale_u = pscale;
+        if (sa != s && u + 1 < u1) {
+            load_x(sa);
+            pscale = ps[sa];
+        }
         __syncthreads();
-        // ---- pass C: radix 16 over k1, power, store ----
-        float *Pt = P + (int64_t)t * ld + base;
-        const int hi = (int)min<int64_t>(L, n - base);
+        // ---- pass C of item u interleaved with pass A of item u + 1 ----
+        // (cc is free: pass B of u read it before the barrier)
+        // Power stores go through a buffer resource spanning this segment's
+        // kept outputs P_t[sV, sV + hi - D): offsets are taken relative to
+        // output D of the segment, so a discarded output (n < D) has a
+        // negative offset, which wraps past the resource's range, and a store
+        // beyond the input's end is past it too; the hardware drops both.
+        const int64_t base = s * V - D;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            P + (int64_t)t * ld + s * V, 0, 4 * ((int)min<int64_t>(L, n - base) - D), kBufWord3);
+        float *const otw = ot[w];
+        uint32_t pa[2][8];
 #pragma unroll
         for (int gam = 0; gam < 4; ++gam) {
+            pass_a(2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
             const uint32_t *src = bbr + 4 * gam * BJ;     // j = 16 (4w + gam) + col
             const uint4 bop = make_uint4(src[0], src[4], src[8], src[12]);
+            pass_a(2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     // output n = j + 128 m, m = 8 h + 2 g + i
-                    const int nn = nbase + 16 * gam + 1024 * h + 128 * i;
-                    if (nn >= D && nn < hi)
-                        __builtin_nontemporal_store((d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale, Pt + nn);
+                    otw[(8 * h + 2 * g + i) * OT_ROW + 16 * gam + col] =
+                        (d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale_u;
                 }
             }
         }
-        t = tn;
-        if (t == 0) ++s;
+        // 16 rows of 64 consecutive outputs per wave (the wave's own region:
+        // its LDS accesses are executed in order, no barrier needed)
+        const int off0 = 4 * (64 * w + l - D);
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(otw[m * OT_ROW + l]), rs, off0 + 512 * m, 0,
+                                                  kNonTemporal);
+        next_a();
+        store_a(pa);
+        __syncthreads();
+        if (++t == M) { t = 0; ++s; }
     }
 }
 
