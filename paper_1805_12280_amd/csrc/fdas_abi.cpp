@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -75,6 +76,9 @@ struct fdas_plan {
     void *d_mat = nullptr;     // 16-bit DFT matrices of the inverse passes
     void *d_stage = nullptr;   // scaled segment spectra of one call (16-bit plans)
     hipEvent_t stage_free = nullptr;  // recorded after each call that used d_stage
+    mutable std::mutex stage_mu;      // orders the enqueues of calls that share d_stage
+    mutable hipStream_t stage_stream = nullptr;
+    mutable bool stage_used = false;
     c32 *d_H = nullptr;        // [M][L], permuted frequency order per template
     c32 *d_tw = nullptr;       // [L]
     c32 *d_taps = nullptr;     // [M][kp], zero beyond tap_len
@@ -277,13 +281,18 @@ FDAS_API int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, f
         m.stage = plan->d_stage;
         m.P = d_power;
         m.ld = ld_power;
-        // calls on one plan share its staging buffer: each call waits for the
-        // previous one (on whatever stream it ran) before writing it
+        // calls on one plan share its staging buffer: each call's work waits
+        // for the previous call's (stream order already gives that when both
+        // were enqueued on the same stream)
         hipStream_t st = (hipStream_t)hip_stream;
-        hipError_t e = hipStreamWaitEvent(st, plan->stage_free, 0);
+        std::lock_guard<std::mutex> lock(plan->stage_mu);
+        hipError_t e = hipSuccess;
+        if (plan->stage_used && plan->stage_stream != st) e = hipStreamWaitEvent(st, plan->stage_free, 0);
         if (e == hipSuccess) e = fdas::launch_mixed(m, st);
         if (e == hipSuccess) e = hipEventRecord(plan->stage_free, st);
         if (e != hipSuccess) return hip_fail(e, "launching the 16-bit FDFIR kernels");
+        plan->stage_used = true;
+        plan->stage_stream = st;
         return FDAS_OK;
     }
     fdas::FusedArgs a;
