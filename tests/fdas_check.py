@@ -9,7 +9,8 @@ import numpy as np
 
 FP32_TOL = 1e-4      # max |P_gpu - P_ref| / max P_ref for the float32 path
 MIXED_TOL = 2e-3     # the same for the 16-bit plans (FP16 storage)
-BF16_BOUND = 1e-2    # BF16 storage: 8 significant bits (provisional bound)
+BF16_BOUND = 2e-2    # BF16 storage (8 significant bits) misses 2e-3; a regression
+                     # guard at twice the worst error measured over the test cases
 TOPK = 16
 
 
