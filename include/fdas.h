@@ -99,8 +99,9 @@ typedef struct {
  *              the inverse FFT passes run on the matrix cores with 16-bit
  *              operands and float32 accumulation, each segment scaled by a
  *              power of two; the power plane is float32.  Mixed plans need
- *              seg_fft = 2048 (or 0) and support fdas_convolve only; the
- *              other calls return FDAS_EUNSUPPORTED.  A mixed plan also
+ *              seg_fft = 2048 (or 0) and support fdas_convolve and
+ *              fdas_convolve_batched; fdas_tdfir and fdas_segment_fft
+ *              return FDAS_EUNSUPPORTED.  A mixed plan also
  *              holds a staging buffer of 16 KB per segment of input_len for
  *              the scaled segment spectra of one call.
  *   hip_stream stream on which the plan is built; the call waits for that
@@ -185,7 +186,8 @@ int fdas_batched_workspace_bytes(const fdas_plan *plan, const int64_t *n, int32_
  * fly to its topk largest cells instead of being written.
  *
  *   d_in       host array [count] of device complex64 pointers (8-byte
- *              aligned), array a holding n[a] points.
+ *              aligned), array a holding n[a] points; for a mixed plan,
+ *              pointers to 16-bit (re, im) pairs, 4-byte aligned.
  *   n          host int64 [count], 1 <= n[a] <= input_len, n[a] < 2^31.
  *   d_out      device fdas_cand [count][topk]: row a lists array a's topk
  *              cells (t, bin) with the largest P_t[bin], ordered by P
@@ -195,10 +197,12 @@ int fdas_batched_workspace_bytes(const fdas_plan *plan, const int64_t *n, int32_
  *   d_workspace, workspace_bytes  device scratch of at least
  *              fdas_batched_workspace_bytes(plan, n, count, topk) bytes,
  *              256-byte aligned, owned by the caller; no state is kept in
- *              it between calls.
- * Asynchronous on hip_stream (two kernel launches, no copies, no memsets,
- * no allocation), so the call can be captured into a HIP graph.  Calls
- * that share a workspace must not overlap.
+ *              it between calls.  For a mixed plan it also holds the scaled
+ *              spectra of every segment of the batch (16 KB per segment).
+ * Asynchronous on hip_stream (two kernel launches, three for a mixed plan;
+ * no copies, no memsets, no allocation), so the call can be captured into
+ * a HIP graph.  Calls that share a workspace must not overlap.  A mixed
+ * plan computes every cell exactly as its fdas_convolve does.
  * Errors: FDAS_EINVAL (NULL/misaligned pointers, sizes out of range, or a
  * workspace that is too small), FDAS_EHIP.
  */

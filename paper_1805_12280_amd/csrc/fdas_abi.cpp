@@ -71,6 +71,7 @@ struct fdas_plan {
     int topk_per_cu = 1;
     int prec = 0;              // 0 float32, 1 binary16, 2 bfloat16
     int mixed_per_cu = 1;
+    int mixed_topk_per_cu = 1;
     int eh = 0;                // template spectra scaled by 2^eh in 16-bit storage
     uint32_t *d_H16 = nullptr; // [M][2048] packed 16-bit pairs, pass-A lane order
     void *d_mat = nullptr;     // 16-bit DFT matrices of the inverse passes
@@ -242,6 +243,7 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
         if (e != hipSuccess) { free_plan(p); return hip_fail(e, "building 16-bit template spectra"); }
         p->resident_bytes += (int64_t)(bytes16 + fdas::mixed_matrix_bytes() + stage);
         p->mixed_per_cu = fdas::mixed_blocks_per_cu(prec == 2);
+        p->mixed_topk_per_cu = fdas::mixed_topk_blocks_per_cu(prec == 2);
     }
     *out = p;
     return FDAS_OK;
@@ -351,7 +353,8 @@ struct BatchShape {
     fdas::BatchSet bs;
     int64_t items = 0, grid = 0;
     int max_slots = 0;
-    size_t off_hdr = 0, off_nslots = 0, bytes = 0;
+    size_t off_hdr = 0, off_nslots = 0, off_xstage = 0, bytes = 0;
+    int64_t segments = 0;
 };
 
 int batch_shape(const fdas_plan *plan, const int64_t *n, int32_t count, int32_t topk, BatchShape &sh)
@@ -374,7 +377,8 @@ int batch_shape(const fdas_plan *plan, const int64_t *n, int32_t count, int32_t 
     }
     sh.bs.item_begin[count] = acc;
     sh.items = acc;
-    const int64_t resident = (int64_t)plan->topk_per_cu * std::max(1, plan->num_cu);
+    const int per_cu = plan->prec ? plan->mixed_topk_per_cu : plan->topk_per_cu;
+    const int64_t resident = (int64_t)per_cu * std::max(1, plan->num_cu);
     sh.grid = std::max<int64_t>(1, std::min(acc, resident));
     // most arrays any workgroup's contiguous item range touches
     int ms = 1, a0 = 0;
@@ -391,6 +395,12 @@ int batch_shape(const fdas_plan *plan, const int64_t *n, int32_t count, int32_t 
     sh.off_hdr = align_up(lists * topk * sizeof(fdas_cand));
     sh.off_nslots = sh.off_hdr + align_up(lists * 2 * sizeof(int));
     sh.bytes = sh.off_nslots + align_up((size_t)sh.grid * sizeof(int));
+    sh.segments = acc / plan->M;
+    if (plan->prec) {
+        // 16-bit plans: the scaled spectra of every segment of the batch
+        sh.off_xstage = sh.bytes;
+        sh.bytes += align_up(fdas::mixed_stage_bytes(sh.segments));
+    }
     return FDAS_OK;
 }
 
@@ -416,7 +426,6 @@ FDAS_API int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_i
     BatchShape sh;
     int rc = batch_shape(plan, n, count, topk, sh);
     if (rc != FDAS_OK) return rc;
-    if (plan->prec != 0) return fail(FDAS_EUNSUPPORTED, "fdas_convolve_batched takes float32 plans only");
     if (!d_in) return fail(FDAS_EINVAL, "d_in is NULL");
     if (!d_out || ((uintptr_t)d_out) % 4) return fail(FDAS_EINVAL, "d_out is NULL or not 4-byte aligned");
     if (!d_workspace || ((uintptr_t)d_workspace) % kAlign)
@@ -424,8 +433,34 @@ FDAS_API int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_i
     if (workspace_bytes < sh.bytes)
         return fail(FDAS_EINVAL, "workspace of %zu bytes, %zu needed", workspace_bytes, sh.bytes);
     for (int a = 0; a < count; ++a) {
-        if (!d_in[a] || ((uintptr_t)d_in[a]) % 8) return fail(FDAS_EINVAL, "d_in[%d] is NULL or misaligned", a);
+        if (!d_in[a] || ((uintptr_t)d_in[a]) % (plan->prec ? 4 : 8))
+            return fail(FDAS_EINVAL, "d_in[%d] is NULL or misaligned", a);
         sh.bs.x[a] = (const c32 *)d_in[a];
+    }
+    if (plan->prec) {
+        fdas::MixedTopkArgs m;
+        m.bs = &sh.bs;
+        m.H16 = plan->d_H16;
+        m.mat = plan->d_mat;
+        m.twL = plan->d_tw;
+        m.M = plan->M;
+        m.D = plan->D;
+        m.V = plan->V;
+        m.K = topk;
+        m.eh = plan->eh;
+        m.bf = plan->prec == 2;
+        m.items = sh.items;
+        m.grid = sh.grid;
+        m.segments = sh.segments;
+        m.xstage = (char *)d_workspace + sh.off_xstage;
+        m.stage = d_workspace;
+        m.hdr = (char *)d_workspace + sh.off_hdr;
+        m.nslots = (int *)((char *)d_workspace + sh.off_nslots);
+        m.max_slots = sh.max_slots;
+        m.out = d_out;
+        hipError_t e = fdas::launch_mixed_topk(m, (hipStream_t)hip_stream);
+        if (e != hipSuccess) return hip_fail(e, "launching the 16-bit batched FDFIR kernels");
+        return FDAS_OK;
     }
     fdas::TopkArgs a;
     a.bs = &sh.bs;

@@ -10,23 +10,12 @@
 // current array, and a second small kernel merges the per-workgroup lists of
 // each array.
 //
-// Order of cells: power descending, then template ascending, then bin
-// ascending (a strict total order, since (template, bin) is unique).
+// Order of cells (Cand, beats in fdas_internal.h): power descending, then
+// template ascending, then bin ascending.
 #include "fdas_internal.h"
 #include "seg_fft.h"
 
 namespace fdas {
-
-struct Cand {        // same layout as fdas_cand
-    int t;
-    int bin;
-    float p;
-};
-
-__device__ __forceinline__ bool beats(float pa, int ta, int ia, float pb, int tb, int ib)
-{
-    return pa > pb || (pa == pb && (ta < tb || (ta == tb && ia < ib)));
-}
 
 // Work item u in [0, items) of the batch is (array a, segment s, template t),
 // ordered by array, then segment, then template; bs.item_begin[a] is the
@@ -347,9 +336,15 @@ hipError_t launch_topk(const TopkArgs &a, hipStream_t st)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)a.bs->count), dim3(MERGE_THREADS), 0, st,
-                       (const Cand *)a.stage, (const int2 *)a.hdr, (const int *)a.nslots,
-                       (int)a.grid, a.max_slots, a.K, (Cand *)a.out);
+    return launch_topk_merge(a.stage, a.hdr, a.nslots, (int)a.grid, a.max_slots, a.K, a.bs->count, a.out, st);
+}
+
+hipError_t launch_topk_merge(const void *stage, const void *hdr, const int *nslots, int nb, int max_slots,
+                             int K, int count, void *out, hipStream_t st)
+{
+    if (nb > MERGE_THREADS * MERGE_Q) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)count), dim3(MERGE_THREADS), 0, st,
+                       (const Cand *)stage, (const int2 *)hdr, nslots, nb, max_slots, K, (Cand *)out);
     return hipGetLastError();
 }
 

@@ -47,6 +47,20 @@ struct BatchSet {
     int count;
 };
 
+// One candidate cell (same layout as fdas_cand) and the order of cells:
+// power descending, then template ascending, then bin ascending (a strict
+// total order, since (template, bin) is unique).
+struct Cand {
+    int t;
+    int bin;
+    float p;
+};
+
+__device__ __forceinline__ bool beats(float pa, int ta, int ia, float pb, int tb, int ib)
+{
+    return pa > pb || (pa == pb && (ta < tb || (ta == tb && ia < ib)));
+}
+
 struct TopkArgs {
     const BatchSet *bs;
     const void *H;
@@ -92,6 +106,26 @@ size_t mixed_stage_bytes(int64_t segments);
 hipError_t launch_mat_table(bool bf, void *tab, hipStream_t st);
 hipError_t launch_mixed(const MixedArgs &a, hipStream_t st);
 hipError_t launch_topk(const TopkArgs &a, hipStream_t st);
+// merge of the per-workgroup candidate lists of each array (second kernel
+// of both batched forms); nb = workgroups of the first kernel
+hipError_t launch_topk_merge(const void *stage, const void *hdr, const int *nslots, int nb, int max_slots,
+                             int K, int count, void *out, hipStream_t st);
+
+struct MixedTopkArgs {
+    const BatchSet *bs;   // x[] hold 16-bit pairs
+    const void *H16, *mat;
+    const c32 *twL;
+    int M, D, V, K, eh;
+    bool bf;
+    int64_t items, grid, segments;
+    void *xstage;         // mixed_stage_bytes(segments)
+    void *stage, *hdr;
+    int *nslots;
+    int max_slots;
+    void *out;
+};
+int mixed_topk_blocks_per_cu(bool bf);
+hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st);
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
 
 }  // namespace fdas

@@ -430,6 +430,365 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
 }
 
 // ---------------------------------------------------------------------------
+// batched form: many spectra, each reduced to its top-K cells
+// ---------------------------------------------------------------------------
+
+// Forward transforms of every segment of a batch: block sg is global segment
+// sg; items are ordered (array, segment, template), so the global segment of
+// item u is u / M and array a's segments start at item_begin[a] / M.
+template <bool BF>
+__global__ __launch_bounds__(128) void mixed_fwd_batch_kernel(BatchSet bs, int M, const c32 *__restrict__ twL,
+                                                              int D, int V, int eh, float4 *__restrict__ Xs,
+                                                              float *__restrict__ ps)
+{
+    using SG = Seg<2048>;
+    using HF = Half<BF>;
+    constexpr int L = mix::L, T = mix::T;
+    __shared__ c32 lds[2 * SG::LDS_ELEMS];
+    __shared__ float s_max[2];
+    c32 *bufA = lds, *bufC = lds + SG::LDS_ELEMS;
+    const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
+    const int64_t sg = blockIdx.x;
+    int a = 0;
+    while (bs.item_begin[a + 1] <= sg * M) ++a;        // uniform: at most 128 steps
+    const int64_t n = bs.n[a];
+    const int64_t base = (sg - bs.item_begin[a] / M) * V - D;
+    const uint32_t *x16 = reinterpret_cast<const uint32_t *>(bs.x[a]);
+
+    c32 v[16];
+    {
+        const uint32_t *xs = x16 + base;
+        const int lo = (int)max<int64_t>(0, -base), hi = (int)min<int64_t>(L, n - base);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = tau + T * m;
+            v[m] = (j >= lo && j < hi) ? HF::unpack(xs[j]) : mk(0.f, 0.f);
+        }
+    }
+    {
+        c32 tw0[16], tw1[16];
+        SG::twiddles(tau, twL, tw0, tw1);
+        SG::fwd0(tau, v, tw0);
+        SG::put_a(tau, v, bufA);
+        __syncthreads();
+        SG::fwd1(tau, v, bufA, tw1);
+    }
+    SG::put_c(tau, v, bufC);
+    __syncthreads();
+    SG::fwd2(tau, v, bufC);
+    __syncthreads();
+    float mx = 0.f;
+    {
+        c32 *dst = lds + SG::k1_of(tau) + 34 * SG::p_of(tau);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            dst[17 * (e >> 3) + 272 * (e & 7)] = v[e];
+            mx = fmaxf(mx, fmaxf(fabsf(v[e].re), fabsf(v[e].im)));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (l == 0) s_max[w] = mx;
+    __syncthreads();
+    mx = fmaxf(s_max[0], s_max[1]);
+    int es = 0;
+    if (mx > 0.f) {
+        int ex;
+        frexpf(2.f * mx, &ex);
+        es = 4 - ex;
+    }
+    const float sigma = ldexpf(1.f, es);
+    if (tau == 0) ps[sg] = ldexpf(1.f, -2 * (es + eh));
+    const c32 *src = lds + col + 136 * w + 544 * g;
+    float4 *out = Xs + sg * (L / 2) + tau;
+#pragma unroll
+    for (int vp = 0; vp < 8; ++vp) {
+        const c32 z0 = src[17 * vp], z1 = src[17 * vp + 272];
+        out[vp * T] = make_float4(z0.re * sigma, z0.im * sigma, z1.re * sigma, z1.im * sigma);
+    }
+}
+
+// The template loop of fdfir_mixed_kernel over the items of a batch, with
+// the power plane replaced by an exact running top-K per array in LDS (the
+// scheme of the float32 batched kernel: a uniform threshold, candidates
+// appended to an LDS list, ranked into the kept list), written to the
+// workspace as one list per array the workgroup touches.
+template <bool BF>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void fdfir_mixed_topk_kernel(
+    BatchSet bs, const float4 *__restrict__ Xs, const float *__restrict__ ps, const uint32_t *__restrict__ H16,
+    const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int K, int64_t items,
+    Cand *__restrict__ stage, int2 *__restrict__ hdr, int *__restrict__ nslots, int max_slots)
+{
+    using HF = Half<BF>;
+    constexpr int L = mix::L, T = mix::T, BJ = mix::BJ;
+    __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
+    // the B->C exchange, and after pass C the candidate list (up to L cells)
+    __shared__ __align__(16) uint32_t bx[2 * L];
+    static_assert(mix::BB_WORDS <= 2 * L, "LDS");
+    __shared__ float keptP[2][TOPK_MAX];
+    __shared__ int keptT[2][TOPK_MAX];
+    __shared__ int keptI[2][TOPK_MAX];
+    __shared__ float smax[T];
+    __shared__ int s_cnt;
+    __shared__ float s_thr;
+    uint32_t *bb = bx;
+    float2 *cand = reinterpret_cast<float2 *>(bx);
+
+    const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
+    uint32_t *const ccw = cc + mix::cc_word(2 * g, col, 8 * w);
+    const uint32_t *const ccr = cc + mix::cc_word(4 * w, col, 4 * g);
+    uint32_t *const bbw = bb + mix::bb_word(4 * w + 16 * g, col);
+    const uint32_t *const bbr = bb + mix::bb_word(64 * w + col, 4 * g);
+    const int nbase = 64 * w + col + 256 * g;     // bin of this lane's value (gam, h, i) = 0 within a segment
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
+    if (u0 >= u1) {
+        if (tau == 0) nslots[b] = 0;
+        return;
+    }
+
+    uint2 aA[8];
+#pragma unroll
+    for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
+    const uint4 aD[2] = {mat[MAT_D + l], mat[MAT_D + 64 + l]};
+    c32 twc[4][2][2];
+#pragma unroll
+    for (int gam = 0; gam < 4; ++gam)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
+                const c32 f = twL[(j * col) & (L - 1)];
+                twc[gam][h][i] = mk(f.re, -f.im);
+            }
+
+    // item u: global segment gs = u / M, template t; array a; its segments
+    // start at global segment seg0
+    int64_t gs = u0 / M;
+    int t = (int)(u0 - gs * M);
+    int a = 0;
+    while (bs.item_begin[a + 1] <= u0) ++a;
+    int64_t seg0 = bs.item_begin[a] / M, seg1 = bs.item_begin[a + 1] / M;
+    // the pass-A item u + 1 runs one phase ahead
+    int64_t gsa = gs;
+    int ta = t;
+    uint4 Hn[4];
+    auto load_h = [&](int tt) {
+        const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)tt * L) + tau * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
+    };
+    c32 X[16];
+    auto load_x = [&](int64_t ss) {
+        const float4 *src = Xs + ss * (L / 2) + tau;
+#pragma unroll
+        for (int vp = 0; vp < 8; ++vp) {
+            const float4 f = src[vp * T];
+            X[2 * vp] = mk(f.x, f.y);
+            X[2 * vp + 1] = mk(f.z, f.w);
+        }
+    };
+    auto pass_a = [&](int gam, uint32_t &c0, uint32_t &c1) {
+        const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
+        const c32 z0 = mul(X[2 * gam], HF::unpack(hw0));
+        const c32 z1 = mul(X[2 * gam + 1], HF::unpack(hw1));
+        const uint2 bop = make_uint2(HF::pack(z0.re, z0.im), HF::pack(z1.re, z1.im));
+        const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
+        c0 = HF::pack(d[0], d[1]);
+        c1 = HF::pack(d[2], d[3]);
+    };
+    auto store_a = [&](const uint32_t (&pa)[2][8]) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa)
+                *reinterpret_cast<uint4 *>(ccw + 16 * c + 4 * aa) =
+                    make_uint4(pa[c][4 * aa], pa[c][4 * aa + 1], pa[c][4 * aa + 2], pa[c][4 * aa + 3]);
+    };
+    auto next_a = [&]() {
+        if (++ta == M) { ta = 0; ++gsa; }
+        load_h(ta);
+    };
+
+    int par = 0, kc = 0, slot = 0;
+    float thr = -1.f;
+    auto flush = [&](int arr) {
+        if (slot < max_slots) {
+            Cand *dst = stage + ((int64_t)b * max_slots + slot) * K;
+            if (tau < kc) {
+                Cand c;
+                c.t = keptT[par][tau];
+                c.bin = keptI[par][tau];
+                c.p = keptP[par][tau];
+                dst[tau] = c;
+            }
+            if (tau == 0) hdr[(int64_t)b * max_slots + slot] = make_int2(arr, kc);
+        }
+        ++slot;
+    };
+
+    if (tau == 0) s_cnt = 0;
+    load_h(ta);
+    load_x(gsa);
+    float pscale = ps[gs];
+    {
+        uint32_t pa[2][8];
+#pragma unroll
+        for (int gam = 0; gam < 8; ++gam) pass_a(gam, pa[0][gam], pa[1][gam]);
+        next_a();
+        store_a(pa);
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    for (int64_t u = u0; u < u1; ++u) {
+        // ---- pass B of item u ----
+        uint32_t pb[2][2][4];
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam) {
+            const uint4 bop = *reinterpret_cast<const uint4 *>(ccr + 16 * gam);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const c32 y = mul(mk(d[2 * i], d[2 * i + 1]), twc[gam][h][i]);
+                    pb[h][i][gam] = HF::pack(y.re, y.im);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                *reinterpret_cast<uint4 *>(bbw + (16 * h + 2 * i) * BJ) =
+                    make_uint4(pb[h][i][0], pb[h][i][1], pb[h][i][2], pb[h][i][3]);
+        const float pscale_u = pscale;
+        if (gsa != gs && u + 1 < u1) {
+            load_x(gsa);
+            pscale = ps[gsa];
+        }
+        __syncthreads();
+        // ---- pass C of item u (powers kept in registers) with pass A of u + 1 ----
+        const int64_t base = (gs - seg0) * V - D;
+        const int hi = (int)min<int64_t>(L, bs.n[a] - base);
+        float pw[4][2][2];
+        uint32_t pa[2][8];
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam) {
+            pass_a(2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
+            const uint32_t *src = bbr + 4 * gam * BJ;
+            const uint4 bop = make_uint4(src[0], src[4], src[8], src[12]);
+            pass_a(2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int nn = nbase + 16 * gam + 1024 * h + 128 * i;
+                    const float p = (d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale_u;
+                    pw[gam][h][i] = (nn >= D && nn < hi) ? p : -1.f;     // -1: not an output
+                }
+            }
+        }
+        next_a();
+        store_a(pa);
+        // ---- top-K of item u's cells, merged into the workgroup's list ----
+        float mx = -1.f;
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) mx = fmaxf(mx, pw[gam][h][i]);
+        float th = thr;
+        if (kc < K) {
+            // no full list yet: the K-th largest per-work-item maximum is a
+            // lower bound of this item's K-th largest cell
+            smax[tau] = mx;
+            __syncthreads();
+            int gt = 0, ge = 0;
+            for (int q = 0; q < T; ++q) {
+                const float o = smax[q];
+                gt += o > mx;
+                ge += o >= mx;
+            }
+            if (gt < K && ge >= K) s_thr = mx;
+            __syncthreads();
+            th = s_thr;
+        }
+        bool any = false;
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) any |= (pw[gam][h][i] >= 0.f && pw[gam][h][i] >= th);
+        // (also the barrier after pass C's reads of bb and pass A's writes of cc)
+        if (__syncthreads_or(any)) {
+#pragma unroll
+            for (int gam = 0; gam < 4; ++gam)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        if (pw[gam][h][i] >= 0.f && pw[gam][h][i] >= th) {
+                            const int c = atomicAdd(&s_cnt, 1);
+                            cand[c] = make_float2(pw[gam][h][i],
+                                                  __int_as_float(nbase + 16 * gam + 1024 * h + 128 * i));
+                        }
+            __syncthreads();
+            const int cnt = s_cnt;
+            const int total = kc + cnt;
+            for (int e = tau; e < total; e += T) {
+                float pe;
+                int te, ie;
+                if (e < kc) {
+                    pe = keptP[par][e];
+                    te = keptT[par][e];
+                    ie = keptI[par][e];
+                } else {
+                    const float2 c = cand[e - kc];
+                    pe = c.x;
+                    te = t;
+                    ie = (int)(base + __float_as_int(c.y));
+                }
+                int rank = 0;
+                for (int f = 0; f < kc; ++f) rank += beats(keptP[par][f], keptT[par][f], keptI[par][f], pe, te, ie);
+                for (int f = 0; f < cnt; ++f) {
+                    const float2 c = cand[f];
+                    rank += beats(c.x, t, (int)(base + __float_as_int(c.y)), pe, te, ie);
+                }
+                if (rank < K) {
+                    keptP[par ^ 1][rank] = pe;
+                    keptT[par ^ 1][rank] = te;
+                    keptI[par ^ 1][rank] = ie;
+                }
+            }
+            __syncthreads();
+            par ^= 1;
+            kc = min(K, total);
+            thr = kc == K ? keptP[par][K - 1] : -1.f;
+            if (tau == 0) s_cnt = 0;        // read again only after the next item's barriers
+        }
+        // ---- next item ----
+        if (++t == M) {
+            t = 0;
+            if (++gs == seg1) {
+                flush(a);
+                kc = 0;
+                thr = -1.f;
+                if (++a < bs.count) {
+                    seg0 = seg1;
+                    seg1 = bs.item_begin[a + 1] / M;
+                }
+            }
+        }
+    }
+    if (kc > 0) flush(a);
+    if (tau == 0) nslots[b] = min(slot, max_slots);
+}
+
+// ---------------------------------------------------------------------------
 
 size_t mixed_matrix_bytes() { return MAT_BYTES; }
 
@@ -457,6 +816,36 @@ int mixed_blocks_per_cu(bool bf)
     hipError_t e = bf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel<true>, 128, 0)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel<false>, 128, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+int mixed_topk_blocks_per_cu(bool bf)
+{
+    int nb = 0;
+    hipError_t e = bf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_topk_kernel<true>, 128, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_topk_kernel<false>, 128, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st)
+{
+    float4 *Xs = (float4 *)a.xstage;
+    float *ps = (float *)((char *)a.xstage + (size_t)a.segments * mix::L * sizeof(c32));
+    const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
+    if (a.bf) {
+        hipLaunchKernelGGL(mixed_fwd_batch_kernel<true>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs, ps);
+        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<true>, gi, blk, 0, st, *a.bs, Xs, ps, (const uint32_t *)a.H16,
+                           a.twL, (const uint4 *)a.mat, a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage,
+                           (int2 *)a.hdr, a.nslots, a.max_slots);
+    } else {
+        hipLaunchKernelGGL(mixed_fwd_batch_kernel<false>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs,
+                           ps);
+        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<false>, gi, blk, 0, st, *a.bs, Xs, ps, (const uint32_t *)a.H16,
+                           a.twL, (const uint4 *)a.mat, a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage,
+                           (int2 *)a.hdr, a.nslots, a.max_slots);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_topk_merge(a.stage, a.hdr, a.nslots, (int)a.grid, a.max_slots, a.K, a.bs->count, a.out, st);
 }
 
 size_t mixed_stage_bytes(int64_t segments) { return (size_t)segments * (mix::L * sizeof(c32) + sizeof(float)); }

@@ -121,7 +121,8 @@ class Plan:
     seg_fft:  segment transform length L in {1024, 2048, 4096}
     precision: "fp32", or "fp16" / "bf16" for the mixed plans (16-bit input
                and template spectra, matrix-core inverse transforms, float32
-               accumulation and power; L = 2048, convolve() only)
+               accumulation and power; L = 2048; convolve() and
+               convolve_batched() only, inputs as [n, 2] 16-bit tensors)
     """
 
     def __init__(self, taps, tap_len=None, input_len: int = 1 << 22, seg_fft: int = 2048,
@@ -241,9 +242,16 @@ class Plan:
         import torch
         xs = list(xs)
         for x in xs:
-            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64
-                    and x.dim() == 1 and x.is_contiguous()):
-                raise FdasError(FDAS_EINVAL, "each array must be a contiguous CUDA complex64 vector")
+            if self.precision == "fp32":
+                ok = (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64
+                      and x.dim() == 1 and x.is_contiguous())
+                what = "a contiguous CUDA complex64 vector"
+            else:
+                ok = (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.input_dtype()
+                      and x.dim() == 2 and x.shape[1] == 2 and x.is_contiguous())
+                what = f"a contiguous CUDA {self.input_dtype()} tensor [n, 2]"
+            if not ok:
+                raise FdasError(FDAS_EINVAL, f"each array must be {what}")
         count = len(xs)
         if count < 1 or count > MAX_BATCH:
             raise FdasError(FDAS_EINVAL, f"batch of {count} arrays; 1..{MAX_BATCH} supported")

@@ -105,3 +105,31 @@ class PlaneStats:
         ok, bad = self.topk_agree()
         return {"norm_err": self.norm_err, "rrmse": self.rrmse, "max_ref": self.max_ref,
                 "topk_ok": ok, "topk_mismatch": bad[:4]}
+
+
+def check_against_plane(t, b, p, ref_plane, k, tol=FP32_TOL):
+    """GPU top-k list of one array against its FP64 oracle plane."""
+    m, n = ref_plane.shape
+    cells = m * n
+    import oracle
+    want = oracle.topk(ref_plane, k)
+    maxref = float(ref_plane.max()) if cells else 0.0
+    if cells < k:
+        assert np.all(t[cells:] == -1) and np.all(b[cells:] == -1) and np.all(p[cells:] == -1.0)
+    got = [(int(t[r]), int(b[r]), float(p[r])) for r in range(min(k, cells))]
+    # each reported power is the oracle's power at that cell
+    for tt, bb, pp in got:
+        assert 0 <= tt < m and 0 <= bb < n
+        assert abs(pp - ref_plane[tt, bb]) <= tol * maxref + 1e-30
+    # ordered by (P desc, t asc, bin asc)
+    for r in range(len(got) - 1):
+        a_, c_ = got[r], got[r + 1]
+        assert a_[2] > c_[2] or (a_[2] == c_[2] and (a_[0], a_[1]) < (c_[0], c_[1]))
+    # same set as the oracle's, up to swaps within the tolerance of the k-th value
+    kth = want[-1][2]
+    gs = {(a_, b_) for a_, b_, _ in got}
+    ws = {(a_, b_) for a_, b_, _ in want}
+    for c in gs - ws:
+        assert ref_plane[c] >= kth - tol * maxref, ("extra", c)
+    for c in ws - gs:
+        assert ref_plane[c] <= kth + tol * maxref, ("missing", c)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from fdas_check import FP32_TOL
+from fdas_check import FP32_TOL, check_against_plane
 from paper_1805_12280_amd import datagen
 
 pytestmark = pytest.mark.gpu
@@ -34,33 +34,6 @@ def env():
 def cands_np(fdas, raw):
     t, b, p = fdas.split_candidates(raw)
     return t.cpu().numpy(), b.cpu().numpy(), p.cpu().numpy()
-
-
-def check_against_plane(t, b, p, ref_plane, k, tol=FP32_TOL):
-    """GPU top-k list of one array against its FP64 oracle plane."""
-    m, n = ref_plane.shape
-    cells = m * n
-    want = oracle.topk(ref_plane, k)
-    maxref = float(ref_plane.max()) if cells else 0.0
-    if cells < k:
-        assert np.all(t[cells:] == -1) and np.all(b[cells:] == -1) and np.all(p[cells:] == -1.0)
-    got = [(int(t[r]), int(b[r]), float(p[r])) for r in range(min(k, cells))]
-    # each reported power is the oracle's power at that cell
-    for tt, bb, pp in got:
-        assert 0 <= tt < m and 0 <= bb < n
-        assert abs(pp - ref_plane[tt, bb]) <= tol * maxref + 1e-30
-    # ordered by (P desc, t asc, bin asc)
-    for r in range(len(got) - 1):
-        a_, c_ = got[r], got[r + 1]
-        assert a_[2] > c_[2] or (a_[2] == c_[2] and (a_[0], a_[1]) < (c_[0], c_[1]))
-    # same set as the oracle's, up to swaps within the tolerance of the k-th value
-    kth = want[-1][2]
-    gs = {(a_, b_) for a_, b_, _ in got}
-    ws = {(a_, b_) for a_, b_, _ in want}
-    for c in gs - ws:
-        assert ref_plane[c] >= kth - tol * maxref, ("extra", c)
-    for c in ws - gs:
-        assert ref_plane[c] <= kth + tol * maxref, ("missing", c)
 
 
 @pytest.mark.parametrize("L,k", [(1024, 16), (2048, 1), (2048, 32), (4096, 16)])

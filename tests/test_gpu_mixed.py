@@ -200,7 +200,6 @@ def test_mixed_plan_errors(torch_cuda, fdas):
     # float32 entry points refuse a 16-bit plan
     out = torch.empty((2, 4000), dtype=torch.float32, device="cuda")
     for call in (lambda: plan.tdfir(xa, out=out),
-                 lambda: plan.convolve_batched([torch.from_numpy(x).cuda()], topk=4),
                  lambda: plan.segment_fft(torch.zeros((1, 2048), dtype=torch.complex64, device="cuda"))):
         with pytest.raises(fdas.FdasError) as ei:
             call()
@@ -210,4 +209,94 @@ def test_mixed_plan_errors(torch_cuda, fdas):
         with pytest.raises(fdas.FdasError) as ei:
             plan.convolve(bad, out=out)
         assert ei.value.code == fdas.FDAS_EINVAL
+        with pytest.raises(fdas.FdasError) as ei:
+            plan.convolve_batched([bad], topk=4)
+        assert ei.value.code == fdas.FDAS_EINVAL
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# batched form of the 16-bit plans
+# ---------------------------------------------------------------------------
+
+def plane_topk(P, k):
+    """Top-k cells of a float32 plane, ordered (P desc, t asc, bin asc)."""
+    m, n = P.shape
+    flat = P.reshape(-1)
+    take = min(k, flat.size)
+    idx = np.argpartition(-flat, take - 1)[:take] if flat.size > take else np.arange(flat.size)
+    thr = flat[idx].min()
+    idx = np.nonzero(flat >= thr)[0]                    # every cell tied with the k-th
+    order = np.lexsort((idx % n, idx // n, -flat[idx]))[:take]
+    idx = idx[order]
+    return [(int(i // n), int(i % n), float(flat[i])) for i in idx]
+
+
+BATCH_LENGTHS = [1, 2015, 2017, 5000, 30011, 70001]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_batched_equals_plane(torch_cuda, fdas, prec):
+    """Every cell of the batched call is computed as the plane call computes
+    it, so each array's top-16 is the top-16 of its 16-bit plane, exactly."""
+    torch = torch_cuda
+    x_all, bank = datagen.random_case(31, 140000, 5, 77)
+    xs = [x_all[(37 * i) % 1000:(37 * i) % 1000 + n] for i, n in enumerate(BATCH_LENGTHS)]
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(BATCH_LENGTHS), seg_fft=2048, precision=prec)
+    dev = [to16(torch, x, prec) for x in xs]
+    raw = plan.convolve_batched(dev, topk=16)
+    torch.cuda.synchronize()
+    t, b, p = fdas.split_candidates(raw)
+    t, b, p = t.cpu().numpy(), b.cpu().numpy(), p.cpu().numpy()
+    for a, x in enumerate(dev):
+        P = plan.convolve(x).cpu().numpy()
+        want = plane_topk(P, 16)
+        got = [(int(t[a, r]), int(b[a, r]), float(p[a, r])) for r in range(len(want))]
+        _say(f"[mixed batched] {prec} array {a} n={x.shape[0]}: top {got[0]}")
+        assert got == want, (a, got[:4], want[:4])
+        if len(want) < 16:
+            assert np.all(t[a, len(want):] == -1) and np.all(p[a, len(want):] == -1.0)
+    plan.close()
+
+
+def test_mixed_batched_against_oracle(torch_cuda, fdas):
+    """FP16 batched candidates against the oracle's whole plane of each array
+    (original complex64 input), at the 16-bit tolerance."""
+    from fdas_check import check_against_plane
+    torch = torch_cuda
+    x_all, bank = datagen.random_case(32, 140000, 4, 60)
+    lengths = [3, 4000, 33333, 100000]
+    xs = [x_all[:n] for n in lengths]
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(lengths), seg_fft=2048, precision="fp16")
+    raw = plan.convolve_batched([to16(torch, x, "fp16") for x in xs], topk=16)
+    torch.cuda.synchronize()
+    t, b, p = fdas.split_candidates(raw)
+    t, b, p = t.cpu().numpy(), b.cpu().numpy(), p.cpu().numpy()
+    for a, x in enumerate(xs):
+        ref = oracle.power(x, bank.taps, bank.tap_len)
+        check_against_plane(t[a], b[a], p[a], ref, 16, tol=MIXED_TOL)
+    plan.close()
+
+
+def test_mixed_batched_graph_replays(torch_cuda, fdas):
+    torch = torch_cuda
+    x_all, bank = datagen.random_case(33, 90000, 6, 40)
+    lengths = [9000, 45000, 90000]
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(lengths), seg_fft=2048, precision="bf16")
+    dev = [to16(torch, x_all[:n], "bf16") for n in lengths]
+    ws = torch.empty(plan.batched_workspace_bytes(lengths, 8), dtype=torch.uint8, device="cuda")
+    out = torch.empty((3, 8, 3), dtype=torch.int32, device="cuda")
+    eager = plan.convolve_batched(dev, topk=8, out=out, workspace=ws).clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        plan.convolve_batched(dev, topk=8, out=out, workspace=ws)
+    for r in range(3):
+        out.fill_(-5)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), r
+        plan.convolve(dev[1])                     # eager work between replays
+        torch.cuda.synchronize()
     plan.close()
