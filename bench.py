@@ -143,23 +143,40 @@ def batched_leg(torch, fdas, steps, warmup):
     flops = sum(nominal_flops(n, m, best, bank.k_max) for n in batch.lengths)
     tflops = flops / (ms * 1e-3) / 1e12
     plan.close()
-    return {"workload": batch.name, "arrays": len(dev), "points": sum(batch.lengths),
-            "topk": 16, "seg_fft": best, "autotune_ms": tuned, "graph": True,
-            "ms_per_step": ms, "value": samples / (ms * 1e-3), "unit": "template-samples/s",
-            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
+    res = {"workload": batch.name, "arrays": len(dev), "points": sum(batch.lengths),
+           "topk": 16, "seg_fft": best, "autotune_ms": tuned, "graph": True,
+           "ms_per_step": ms, "value": samples / (ms * 1e-3), "unit": "template-samples/s",
+           "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
+    # the same batch on the 16-bit plans (L = 2048), also graph-replayed
+    for prec in ("fp16", "bf16"):
+        plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(batch.lengths), seg_fft=2048, precision=prec)
+        dev16 = [torch.view_as_real(x).to(plan.input_dtype()).contiguous() for x in dev]
+        ws = torch.empty(plan.batched_workspace_bytes(batch.lengths, 16), dtype=torch.uint8, device="cuda:0")
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            plan.convolve_batched(dev16, topk=16, out=out, workspace=ws)
+        ms16 = time_calls(torch, g.replay, steps, warmup)
+        res[prec] = {"ms_per_step": ms16, "value": samples / (ms16 * 1e-3), "speedup_vs_fp32": ms / ms16,
+                     "workspace_bytes": int(ws.numel())}
+        log(f"batched {prec}: {ms16:.3f} ms/step ({ms / ms16:.2f}x fp32)")
+        plan.close()
+        del ws, dev16
+    return res
 
 
 SERVED_BANKS = {"z10": tuple(range(-10, 11)), "z21": tuple(range(-21, 22)), "z42": tuple(range(-42, 43))}
 SERVED_LENGTHS = ((1 << 18, 0.5), (1 << 20, 0.3), (1 << 22, 0.2))
 
 
-def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
+def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4, precision="fp32"):
     """Poisson arrivals of jobs (length 2^18/2^20/2^22 with p = 0.5/0.3/0.2,
     bank of 21/43/85 templates), continuous batching on resident plans,
     top-16 per job.  The saturated rate is measured first (all jobs present at
     t = 0); then arrivals at fractions of it.  Inputs are resident spectra (the
-    stage before filtering runs on the device)."""
+    stage before filtering runs on the device; for a 16-bit precision they are
+    stored as 16-bit pairs)."""
     import numpy as np
     from paper_1805_12280_amd import datagen
     from paper_1805_12280_amd.serve import GpuExecutor, Job, Scheduler, latency_stats
@@ -169,9 +186,13 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
     noise_rng = np.random.default_rng(seed + 1)
     for n, _ in SERVED_LENGTHS:
         pool[n] = [torch.from_numpy(datagen.make_spectrum(n, (), noise_rng)).to("cuda:0") for _ in range(2)]
+        if precision != "fp32":
+            dt = torch.float16 if precision == "fp16" else torch.bfloat16
+            pool[n] = [torch.view_as_real(v).to(dt).contiguous() for v in pool[n]]
     lens = [n for n, _ in SERVED_LENGTHS]
     probs = [p for _, p in SERVED_LENGTHS]
-    ex = GpuExecutor(banks, input_len=1 << 22, topk=16, slots=3, seg_fft={k: 1024 for k in banks})
+    ex = GpuExecutor(banks, input_len=1 << 22, topk=16, slots=3, precision=precision,
+                     seg_fft={k: (1024 if precision == "fp32" else 2048) for k in banks})
     mfree, _ = torch.cuda.mem_get_info()
     budget = int(0.25 * mfree)
 
@@ -210,7 +231,8 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4):
     spec = draw(jobs_per_rate)
     sat = run(spec, [0.0] * len(spec))
     lam = sat["jobs_per_s"]
-    out = {"saturated": sat, "rates": [], "slots": ex.slots, "max_batch": 16, "max_wait_ms": 2.0, "topk": 16,
+    out = {"precision": precision, "saturated": sat, "rates": [], "slots": ex.slots, "max_batch": 16,
+           "max_wait_ms": 2.0, "topk": 16,
            "budget_bytes": budget, "jobs_per_rate": jobs_per_rate}
     for r in rates:
         gaps = rng.exponential(1.0 / (r * lam), size=len(spec)).tolist()
@@ -399,12 +421,13 @@ def main():
             f"{result['batched']['value']:.3e} template-samples/s")
 
     if not args.no_served:
-        result["served"] = served_leg(torch)
-        log("served: " + json.dumps({k: (round(v, 3) if isinstance(v, float) else v)
-                                     for k, v in result["served"]["saturated"].items()}))
-        for st in result["served"]["rates"]:
-            log(f"  offered {st['offered_fraction']:.2f} x saturated: p50 {st['p50_ms']:.2f} ms, "
-                f"p99 {st['p99_ms']:.2f} ms, {st['jobs_per_s']:.0f} jobs/s")
+        for key, prec in (("served", "fp32"), ("served_fp16", "fp16")):
+            result[key] = served_leg(torch, precision=prec)
+            log(f"{key}: " + json.dumps({k: (round(v, 3) if isinstance(v, float) else v)
+                                         for k, v in result[key]["saturated"].items()}))
+            for st in result[key]["rates"]:
+                log(f"  offered {st['offered_fraction']:.2f} x saturated: p50 {st['p50_ms']:.2f} ms, "
+                    f"p99 {st['p99_ms']:.2f} ms, {st['jobs_per_s']:.0f} jobs/s")
 
     if not args.no_sweeps:
         result["sweeps"] = sweeps_leg(torch, fdas)

@@ -25,7 +25,8 @@ import time
 class Job:
     job_id: int
     bank: str
-    x: object                   # the spectrum (a CUDA complex64 tensor for GpuExecutor)
+    x: object                   # the spectrum (for GpuExecutor: a CUDA complex64 tensor, or
+                                #   [n, 2] 16-bit pairs for a 16-bit executor)
     n: int
     arrival: float              # scheduler clock time of arrival
     admitted: float | None = None
@@ -155,7 +156,7 @@ class GpuExecutor:
     """Batched calls on `slots` streams, with one resident plan per bank."""
 
     def __init__(self, banks: dict, input_len: int, topk: int = 16, slots: int = 2,
-                 seg_fft: dict | None = None, device: str = "cuda:0"):
+                 seg_fft: dict | None = None, device: str = "cuda:0", precision: str = "fp32"):
         import torch
         from . import fdas
         self.torch = torch
@@ -163,10 +164,12 @@ class GpuExecutor:
         self.topk = int(topk)
         self.slots = int(slots)
         self.device = torch.device(device)
+        self.precision = precision
         self.plans = {}
         for name, bank in banks.items():
             L = (seg_fft or {}).get(name, 2048)
-            self.plans[name] = fdas.Plan(bank.taps, bank.tap_len, input_len=input_len, seg_fft=L)
+            self.plans[name] = fdas.Plan(bank.taps, bank.tap_len, input_len=input_len, seg_fft=L,
+                                         precision=precision)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.slots)]
         self.free_streams = list(range(self.slots))
         # per-stream workspace and candidate buffers, grown on demand and then
@@ -176,8 +179,12 @@ class GpuExecutor:
 
     def footprint(self, bank, n):
         # the spectrum while it is admitted, its share of the batch workspace
-        # (bounded by one candidate list per workgroup), and its candidates
-        return 8 * int(n) + 64 * 1024 + 12 * self.topk
+        # (bounded by one candidate list per workgroup, plus for a 16-bit plan
+        # the staged spectra: 16 KB per segment of about 1900 points), and
+        # its candidates
+        if self.precision == "fp32":
+            return 8 * int(n) + 64 * 1024 + 12 * self.topk
+        return 4 * int(n) + 9 * int(n) + 80 * 1024 + 12 * self.topk
 
     def start(self, bank, jobs):
         torch = self.torch

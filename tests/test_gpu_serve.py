@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from fdas_check import FP32_TOL
+from fdas_check import FP32_TOL, MIXED_TOL
 from paper_1805_12280_amd import datagen
 
 pytestmark = pytest.mark.gpu
@@ -27,8 +27,10 @@ def env():
     return torch, fdas
 
 
-def test_mix_equals_alone(env):
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_mix_equals_alone(env, precision):
     torch, fdas = env
+    tol = FP32_TOL if precision == "fp32" else MIXED_TOL
     from paper_1805_12280_amd.serve import GpuExecutor, Job, Scheduler, latency_stats
     banks = {k: datagen.make_bank(v) for k, v in BANKS.items()}
     rng = np.random.default_rng(4)
@@ -38,8 +40,12 @@ def test_mix_equals_alone(env):
         n = int(rng.choice(lengths, p=[0.5, 0.3, 0.2]))
         bank = str(rng.choice(list(banks)))
         x, _ = datagen.random_case(500 + i, n, 1, 1)
-        jobs_spec.append((i, bank, torch.from_numpy(x).cuda(), n, float(rng.exponential(2e-4))))
-    ex = GpuExecutor(banks, input_len=1 << 18, topk=16, slots=3, seg_fft={"z10": 1024, "z21": 2048, "z42": 1024})
+        xd = torch.from_numpy(x).cuda()
+        if precision == "fp16":
+            xd = torch.view_as_real(xd).to(torch.float16).contiguous()
+        jobs_spec.append((i, bank, xd, n, float(rng.exponential(2e-4))))
+    seg = {"z10": 1024, "z21": 2048, "z42": 1024} if precision == "fp32" else {k: 2048 for k in banks}
+    ex = GpuExecutor(banks, input_len=1 << 18, topk=16, slots=3, seg_fft=seg, precision=precision)
     sched = Scheduler(ex, budget_bytes=16 << 20, max_batch=6)
     t0 = time.perf_counter()
     arrivals, t = [], t0
@@ -66,11 +72,16 @@ def test_mix_equals_alone(env):
     # oracle check of the smallest jobs
     for j in [a for a in arrivals if a.n == 1 << 16][:3]:
         b = banks[j.bank]
-        P = oracle.power(j.x.cpu().numpy(), b.taps, b.tap_len)
+        if precision == "fp32":
+            xh = j.x.cpu().numpy()
+        else:                                   # the stored 16-bit input, upcast exactly
+            v = j.x.float().cpu().numpy()
+            xh = (v[:, 0] + 1j * v[:, 1]).astype(np.complex64)
+        P = oracle.power(xh, b.taps, b.tap_len)
         want = oracle.topk(P, 16)
         t_, bin_, p_ = fdas.split_candidates(j.result)
         got = list(zip(t_.tolist(), bin_.tolist()))
         assert got[0] == (want[0][0], want[0][1])
         for (tt, bb), pv in zip(got, p_.tolist()):
-            assert abs(pv - P[tt, bb]) <= FP32_TOL * P.max()
+            assert abs(pv - P[tt, bb]) <= tol * P.max()
     ex.close()
