@@ -50,6 +50,24 @@ template <> struct Half<false> {   // IEEE binary16
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0, 0);
     }
+    // Complex product of two packed binary16 values in packed binary16
+    // arithmetic: t = (a.re b.re, a.re b.im) rounded, then
+    // (t.re - a.im b.im, t.im + a.im b.re) by one fused multiply-add.
+    __device__ static uint32_t cmulp(uint32_t a, uint32_t b)
+    {
+        const h2v av = __builtin_bit_cast(h2v, a), bv = __builtin_bit_cast(h2v, b);
+        const h2v are = {av.x, av.x}, aim = {av.y, av.y}, bsw = {-bv.y, bv.x};
+        const h2v z = __builtin_elementwise_fma(aim, bsw, are * bv);
+        return __builtin_bit_cast(uint32_t, z);
+    }
+    // The scaled spectrum and the pass-B twiddles are held as packed
+    // binary16 (the products Z = X H and b W run in packed arithmetic).
+    using XReg = uint32_t;
+    using TwReg = uint32_t;
+    __device__ static XReg to_x(float re, float im) { return pack(re, im); }
+    __device__ static TwReg to_tw(float re, float im) { return pack(re, im); }
+    __device__ static uint32_t zmul(XReg x, uint32_t h) { return cmulp(x, h); }
+    __device__ static uint32_t twmul(float re, float im, TwReg w) { return cmulp(pack(re, im), w); }
 };
 
 template <> struct Half<true> {    // bfloat16
@@ -69,6 +87,22 @@ template <> struct Half<true> {    // bfloat16
     __device__ static f4v mma32(uint4 a, uint4 b, f4v c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0, 0);
+    }
+    // no packed bfloat16 arithmetic: the products run in float32 and are
+    // rounded once
+    using XReg = c32;
+    using TwReg = c32;
+    __device__ static XReg to_x(float re, float im) { return mk(re, im); }
+    __device__ static TwReg to_tw(float re, float im) { return mk(re, im); }
+    __device__ static uint32_t zmul(XReg x, uint32_t h)
+    {
+        const c32 z = mul(x, unpack(h));
+        return pack(z.re, z.im);
+    }
+    __device__ static uint32_t twmul(float re, float im, TwReg w)
+    {
+        const c32 y = mul(mk(re, im), w);
+        return pack(y.re, y.im);
     }
 };
 
@@ -278,7 +312,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
 #pragma unroll
     for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
     const uint4 aD[2] = {mat[MAT_D + l], mat[MAT_D + 64 + l]};
-    c32 twc[4][2][2];
+    typename HF::TwReg twc[4][2][2];
 #pragma unroll
     for (int gam = 0; gam < 4; ++gam)
 #pragma unroll
@@ -287,7 +321,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
             for (int i = 0; i < 2; ++i) {
                 const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
                 const c32 f = twL[(j * col) & (L - 1)];        // exp(-2 pi i j k1 / L)
-                twc[gam][h][i] = mk(f.re, -f.im);
+                twc[gam][h][i] = HF::to_tw(f.re, -f.im);
             }
 
     // Items run as a software pipeline over the two exchange buffers: after
@@ -304,23 +338,21 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
 #pragma unroll
         for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
     };
-    c32 X[16];                         // sigma-scaled spectrum of segment sa at zq(w, l, v)
+    typename HF::XReg X[16];           // sigma-scaled spectrum of segment sa at zq(w, l, v)
     auto load_x = [&](int64_t ss) {
         const float4 *src = Xs + ss * (L / 2) + tau;
 #pragma unroll
         for (int vp = 0; vp < 8; ++vp) {
             const float4 f = src[vp * T];
-            X[2 * vp] = mk(f.x, f.y);
-            X[2 * vp + 1] = mk(f.z, f.w);
+            X[2 * vp] = HF::to_x(f.x, f.y);
+            X[2 * vp + 1] = HF::to_x(f.z, f.w);
         }
     };
     // pass A, column set r = 8w + gam: Z = X H rounded once, radix 8 over s
     // (twiddle folded into the matrix); returns c[2g + c][col][r] packed
     auto pass_a = [&](int gam, uint32_t &c0, uint32_t &c1) {
         const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
-        const c32 z0 = mul(X[2 * gam], HF::unpack(hw0));
-        const c32 z1 = mul(X[2 * gam + 1], HF::unpack(hw1));
-        const uint2 bop = make_uint2(HF::pack(z0.re, z0.im), HF::pack(z1.re, z1.im));
+        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
         const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
         c0 = HF::pack(d[0], d[1]);
         c1 = HF::pack(d[2], d[3]);
@@ -366,8 +398,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
                 const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const c32 y = mul(mk(d[2 * i], d[2 * i + 1]), twc[gam][h][i]);
-                    pb[h][i][gam] = HF::pack(y.re, y.im);
+                    pb[h][i][gam] = HF::twmul(d[2 * i], d[2 * i + 1], twc[gam][h][i]);
                 }
             }
         }
@@ -550,7 +581,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
     for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
     const uint4 aD[2] = {mat[MAT_D + l], mat[MAT_D + 64 + l]};
-    c32 twc[4][2][2];
+    typename HF::TwReg twc[4][2][2];
 #pragma unroll
     for (int gam = 0; gam < 4; ++gam)
 #pragma unroll
@@ -559,7 +590,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
             for (int i = 0; i < 2; ++i) {
                 const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
                 const c32 f = twL[(j * col) & (L - 1)];
-                twc[gam][h][i] = mk(f.re, -f.im);
+                twc[gam][h][i] = HF::to_tw(f.re, -f.im);
             }
 
     // item u: global segment gs = u / M, template t; array a; its segments
@@ -578,21 +609,19 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
 #pragma unroll
         for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
     };
-    c32 X[16];
+    typename HF::XReg X[16];
     auto load_x = [&](int64_t ss) {
         const float4 *src = Xs + ss * (L / 2) + tau;
 #pragma unroll
         for (int vp = 0; vp < 8; ++vp) {
             const float4 f = src[vp * T];
-            X[2 * vp] = mk(f.x, f.y);
-            X[2 * vp + 1] = mk(f.z, f.w);
+            X[2 * vp] = HF::to_x(f.x, f.y);
+            X[2 * vp + 1] = HF::to_x(f.z, f.w);
         }
     };
     auto pass_a = [&](int gam, uint32_t &c0, uint32_t &c1) {
         const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
-        const c32 z0 = mul(X[2 * gam], HF::unpack(hw0));
-        const c32 z1 = mul(X[2 * gam + 1], HF::unpack(hw1));
-        const uint2 bop = make_uint2(HF::pack(z0.re, z0.im), HF::pack(z1.re, z1.im));
+        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
         const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
         c0 = HF::pack(d[0], d[1]);
         c1 = HF::pack(d[2], d[3]);
@@ -651,8 +680,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
                 const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const c32 y = mul(mk(d[2 * i], d[2 * i + 1]), twc[gam][h][i]);
-                    pb[h][i][gam] = HF::pack(y.re, y.im);
+                    pb[h][i][gam] = HF::twmul(d[2 * i], d[2 * i + 1], twc[gam][h][i]);
                 }
             }
         }
