@@ -208,22 +208,27 @@ __global__ __launch_bounds__(L / 16) void segfft_kernel(const c32 *__restrict__ 
 // ---------------------------------------------------------------------------
 
 // Tile of TD_TILE outputs per workgroup, TD_R consecutive outputs per
-// work-item.  LDS holds x[i0 - kp .. i0 + TD_TILE) with one pad slot every 8
-// elements, so work-items 8 elements apart hit different banks.
+// work-item.  LDS holds x[i0 - kp .. i0 + TD_TILE) as two planes (real parts,
+// then imaginary parts) with one pad slot every 8 elements: work-items 8
+// elements apart then read 4-byte words 9 apart, so the 64 lanes of a read
+// touch 64 different banks.
 __device__ __forceinline__ int td_skew(int e) { return e + (e >> 3); }
 
 __global__ __launch_bounds__(TD_THREADS) void tdfir_kernel(
     const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ taps,
     const int *__restrict__ tap_len, int M, int kp, int tg, float *__restrict__ P, int64_t ld)
 {
-    extern __shared__ c32 xs[];
+    extern __shared__ float xsf[];
     const int tau = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * TD_TILE;
     const int64_t org = i0 - kp;
     const int span = TD_TILE + kp;
+    float *const xr = xsf, *const xi = xsf + td_skew(span) + 1;
     for (int l = tau; l < span; l += TD_THREADS) {
         const int64_t i = org + l;
-        xs[td_skew(l)] = (i >= 0 && i < n) ? x[i] : mk(0.f, 0.f);
+        const c32 v = (i >= 0 && i < n) ? x[i] : mk(0.f, 0.f);
+        xr[td_skew(l)] = v.re;
+        xi[td_skew(l)] = v.im;
     }
     __syncthreads();
     const int t_end = min(M, (int)(blockIdx.y + 1) * tg);
@@ -237,9 +242,12 @@ __global__ __launch_bounds__(TD_THREADS) void tdfir_kernel(
         for (int blk = 0; blk < nblk; ++blk) {
             const int kb = blk * 8;
             c32 win[15];
+            // window x[i - 7 .. i + 7] of this work-item's outputs: tile
+            // elements l0 + c with l0 = 8 q + 1 (kp and kb are multiples of
+            // 8), whose skewed slots are 9 q + 1 + c + (c + 1) / 8
             const int l0 = TD_R * tau + kp - kb - 7;
 #pragma unroll
-            for (int c = 0; c < 15; ++c) win[c] = xs[td_skew(l0 + c)];
+            for (int c = 0; c < 15; ++c) win[c] = mk(xr[td_skew(l0 + c)], xi[td_skew(l0 + c)]);
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) {
                 const c32 hk = h[kb + kk];
@@ -343,8 +351,9 @@ hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int 
 
 size_t tdfir_lds_bytes(int kp)
 {
+    // two planes of td_skew(span) + 1 floats
     const int span = TD_TILE + kp;
-    return sizeof(c32) * (size_t)(span + span / 8 + 2);
+    return 2 * sizeof(float) * (size_t)(span + span / 8 + 1);
 }
 
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st)
