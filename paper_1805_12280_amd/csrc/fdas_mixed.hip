@@ -2,12 +2,16 @@
 // inverse segment transforms on the matrix cores (FP16 or BF16 operands,
 // FP32 accumulation).  L = 2048.
 //
-// Per segment (once, VALU, float32): gather the 16-bit input, forward FFT
-// (seg_fft.h), redistribute the spectrum X into the lanes that feed pass A
-// (mixed_fft.h), and pick a power-of-two scale sigma from max |X| so the
-// 16-bit operands stay well inside their range.  Per (segment, template):
-// Z = sigma X H (FP32) rounded once to 16 bits, passes A, B, C as matrix
-// products, |y|^2 unscaled exactly by the powers of two, non-temporal store.
+// Two launches per call.  Per segment (mixed_fwd_kernel, float32 VALU):
+// gather the 16-bit input, forward FFT (seg_fft.h), redistribute the
+// spectrum X into the lanes that feed pass A (mixed_fft.h), pick a
+// power-of-two scale sigma from max |X| so the 16-bit operands stay well
+// inside their range, and stage sigma X.  Per (segment, template)
+// (fdfir_mixed_kernel): Z = sigma X H rounded once to 16 bits, passes A, B,
+// C as matrix products, |y|^2 unscaled exactly by the powers of two,
+// full-line streaming stores.  The batched form (mixed_fwd_batch_kernel,
+// fdfir_mixed_topk_kernel) runs the same passes over many spectra and keeps
+// each one's top-K cells instead of its plane.
 #include "fdas_internal.h"
 #include "mixed_fft.h"
 #include "seg_fft.h"
@@ -119,7 +123,6 @@ __device__ __forceinline__ float wentry(int row, int k, double turns)
     }
 }
 
-template <bool BF> __device__ __forceinline__ uint32_t pack_pair_scalar(float a, float b) { return Half<BF>::pack(a, b); }
 
 // ---------------------------------------------------------------------------
 // template spectra in the lane layout of pass A, 16-bit, scaled by 2^eh
@@ -190,13 +193,16 @@ __global__ void mat_table_kernel(uint4 *__restrict__ tab)
 // per segment: forward FFT (float32) and the power-of-two scale
 // ---------------------------------------------------------------------------
 
-// Xs[s][v / 2][tau] holds, as float4 (two complex values), sigma_s X_s at the
-// frequencies zq(w, l, v) and zq(w, l, v + 1) that work-item tau = 64 w + l
-// feeds to pass A; ps[s] = 2^-2(e_s + eh) undoes both scalings of |y|^2.
+// One workgroup transforms the segment of x16 starting at input point base
+// and writes, as float4 (two complex values) per work-item and step,
+// out[v / 2][tau] = sigma X at the frequencies zq(w, l, v), zq(w, l, v + 1)
+// that work-item tau = 64 w + l feeds to pass A, and *ps = 2^-2(e + eh),
+// which undoes both power-of-two scalings of |y|^2 (sigma = 2^e with
+// 2 sigma max|X| <= 16, max over the components of the segment's spectrum).
 template <bool BF>
-__global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restrict__ x16, int64_t n,
-                                                        const c32 *__restrict__ twL, int D, int V, int eh,
-                                                        float4 *__restrict__ Xs, float *__restrict__ ps)
+__device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16, int64_t n, int64_t base,
+                                               const c32 *__restrict__ twL, int eh, float4 *__restrict__ out,
+                                               float *__restrict__ ps)
 {
     using SG = Seg<2048>;
     using HF = Half<BF>;
@@ -205,7 +211,6 @@ __global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restri
     __shared__ float s_max[2];
     c32 *bufA = lds, *bufC = lds + SG::LDS_ELEMS;
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
-    const int64_t s = blockIdx.x, base = s * V - D;
 
     c32 v[16];
     {
@@ -255,20 +260,29 @@ __global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restri
         es = 4 - ex;
     }
     const float sigma = ldexpf(1.f, es);
-    if (tau == 0) ps[s] = ldexpf(1.f, -2 * (es + eh));
+    if (tau == 0) *ps = ldexpf(1.f, -2 * (es + eh));
     // lane (w, l) takes q = zq(w, l, v): slot = (col + 136 w + 544 g)
     // + 17 (v / 2) + 272 (v % 2)
     const c32 *src = lds + col + 136 * w + 544 * g;
-    float4 *out = Xs + s * (L / 2) + tau;
 #pragma unroll
     for (int vp = 0; vp < 8; ++vp) {
         const c32 z0 = src[17 * vp], z1 = src[17 * vp + 272];
-        out[vp * T] = make_float4(z0.re * sigma, z0.im * sigma, z1.re * sigma, z1.im * sigma);
+        out[vp * T + tau] = make_float4(z0.re * sigma, z0.im * sigma, z1.re * sigma, z1.im * sigma);
     }
 }
 
+// Staging layout: segment s at Xs + s * L / 2 (float4), its scale at ps[s].
+template <bool BF>
+__global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restrict__ x16, int64_t n,
+                                                        const c32 *__restrict__ twL, int D, int V, int eh,
+                                                        float4 *__restrict__ Xs, float *__restrict__ ps)
+{
+    const int64_t s = blockIdx.x;
+    forward_scaled<BF>(x16, n, s * V - D, twL, eh, Xs + s * (mix::L / 2), ps + s);
+}
+
 // ---------------------------------------------------------------------------
-// per (segment, template): Z = X H, inverse on the matrix cores, power
+// per (segment, template): Z = X H, inverse on the matrix cores
 // ---------------------------------------------------------------------------
 
 // Buffer resource word 3 of the gfx9 family (32-bit data format; offsets are
@@ -279,6 +293,135 @@ constexpr int kNonTemporal = 2;
 // s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt at their maxima (gfx9 encoding)
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// What one work-item holds for the inverse passes of every item: its lanes
+// of the 16-bit DFT matrices (pass A per column set r = 8 w + gam, with
+// W128^(p r) folded in; the DFT16 of passes B and C) and the pass-B output
+// twiddles W2048^(j k1).  Both template-loop kernels run the passes through
+// these members, so they compute every cell identically.
+template <bool BF> struct MixLane {
+    using HF = Half<BF>;
+    uint2 aA[8];
+    uint4 aD[2];
+    typename HF::TwReg twc[4][2][2];
+
+    __device__ __forceinline__ void init(const uint4 *__restrict__ mat, const c32 *__restrict__ twL, int w, int l)
+    {
+        const int col = l & 15, g = l >> 4;
+#pragma unroll
+        for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
+        aD[0] = mat[MAT_D + l];
+        aD[1] = mat[MAT_D + 64 + l];
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
+                    const c32 f = twL[(j * col) & (mix::L - 1)];        // exp(-2 pi i j k1 / L)
+                    twc[gam][h][i] = HF::to_tw(f.re, -f.im);
+                }
+    }
+    // pass A, column set r = 8w + gam: Z = X H rounded once, radix 8 over s;
+    // returns c[2g][col][r] and c[2g + 1][col][r] packed
+    __device__ __forceinline__ void pass_a(const typename HF::XReg (&X)[16], const uint4 (&Hn)[4], int gam,
+                                           uint32_t &c0, uint32_t &c1) const
+    {
+        const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
+        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
+        const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
+        c0 = HF::pack(d[0], d[1]);
+        c1 = HF::pack(d[2], d[3]);
+    }
+    // pass B: radix 16 over r for p = 4w + gam (reads cc), the twiddle, and
+    // b[col][j], j = 4w + gam + 8 (8h + 2g + i), four consecutive j per store
+    __device__ __forceinline__ void pass_b(const uint32_t *ccr, uint32_t *bbw) const
+    {
+        uint32_t pb[2][2][4];          // [h][i][gam]
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam) {
+            const uint4 bop = *reinterpret_cast<const uint4 *>(ccr + 16 * gam);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int i = 0; i < 2; ++i) pb[h][i][gam] = HF::twmul(d[2 * i], d[2 * i + 1], twc[gam][h][i]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                *reinterpret_cast<uint4 *>(bbw + (16 * h + 2 * i) * mix::BJ) =
+                    make_uint4(pb[h][i][0], pb[h][i][1], pb[h][i][2], pb[h][i][3]);
+    }
+    // pass C, columns j = 16 (4w + gam) + col: radix 16 over k1.  The
+    // operand is read from bb, then each half h of the outputs is one
+    // product whose rows are outputs m = 8h + 2g + i (re, im)
+    __device__ __forceinline__ uint4 pass_c_operand(const uint32_t *bbr, int gam) const
+    {
+        const uint32_t *src = bbr + 4 * gam * mix::BJ;
+        return make_uint4(src[0], src[4], src[8], src[12]);
+    }
+    __device__ __forceinline__ f4v pass_c(int h, uint4 bop) const
+    {
+        return HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+    }
+};
+
+// per-lane LDS bases of the exchanges (the per-group offsets are constants)
+struct MixBases {
+    uint32_t *ccw;         // pass A writes c[2g + c][col][8w + 4a ..]
+    const uint32_t *ccr;   // pass B reads c[4w + gam][col][4g ..]
+    uint32_t *bbw;         // pass B writes b[col][4w + gam + 8 q']
+    const uint32_t *bbr;   // pass C reads b[4g ..][16 (4w + gam) + col]
+    __device__ __forceinline__ MixBases(uint32_t *cc, uint32_t *bb, int w, int l)
+    {
+        const int col = l & 15, g = l >> 4;
+        ccw = cc + mix::cc_word(2 * g, col, 8 * w);
+        ccr = cc + mix::cc_word(4 * w, col, 4 * g);
+        bbw = bb + mix::bb_word(4 * w + 16 * g, col);
+        bbr = bb + mix::bb_word(64 * w + col, 4 * g);
+    }
+    __device__ __forceinline__ void store_a(const uint32_t (&pa)[2][8]) const
+    {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                *reinterpret_cast<uint4 *>(ccw + 16 * c + 4 * a) =
+                    make_uint4(pa[c][4 * a], pa[c][4 * a + 1], pa[c][4 * a + 2], pa[c][4 * a + 3]);
+    }
+};
+
+// template spectra of template t for work-item tau (16 packed values)
+__device__ __forceinline__ void load_h16(const uint32_t *__restrict__ H16, int t, int tau, uint4 (&Hn)[4])
+{
+    const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)t * mix::L) + tau * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
+}
+
+// staged spectrum of global segment s for work-item tau
+template <bool BF>
+__device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t s, int tau,
+                                         typename Half<BF>::XReg (&X)[16])
+{
+    const float4 *src = Xs + s * (mix::L / 2) + tau;
+#pragma unroll
+    for (int vp = 0; vp < 8; ++vp) {
+        const float4 f = src[vp * mix::T];
+        X[2 * vp] = Half<BF>::to_x(f.x, f.y);
+        X[2 * vp + 1] = Half<BF>::to_x(f.z, f.w);
+    }
+}
+
+// Items u = (segment s = u / M, template t = u % M), persistent: each
+// workgroup takes one contiguous range.  They run as a software pipeline
+// over the two exchange buffers: after pass B of item u (cc -> bb) and a
+// barrier, pass C of item u (reads bb) and pass A of item u + 1 (writes cc)
+// run interleaved in one phase, so the matrix products of one overlap the
+// vector work of the other.
 template <bool BF>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_kernel(
     const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const uint32_t *__restrict__ H16,
@@ -286,7 +429,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     float *__restrict__ P, int64_t ld)
 {
     using HF = Half<BF>;
-    constexpr int L = mix::L, T = mix::T, BJ = mix::BJ;
+    constexpr int L = mix::L;
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
     // per-wave transpose of the powers: a wave's pass C yields outputs
@@ -297,89 +440,34 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     __shared__ float ot[2][16 * OT_ROW];
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
-    // per-lane bases of the exchanges (the per-group offsets below are
-    // compile-time constants)
-    uint32_t *const ccw = cc + mix::cc_word(2 * g, col, 8 * w);       // pass A: c[2g + c][col][8w + 4a ..]
-    const uint32_t *const ccr = cc + mix::cc_word(4 * w, col, 4 * g); // pass B: c[4w + gam][col][4g ..]
-    uint32_t *const bbw = bb + mix::bb_word(4 * w + 16 * g, col);     // pass B: b[col][j = 4w + gam + 8 q']
-    const uint32_t *const bbr = bb + mix::bb_word(64 * w + col, 4 * g); // pass C: b[4g ..][16 (4w + gam) + col]
+    const MixBases xb(cc, bb, w, l);
     const int64_t nb = gridDim.x, b = blockIdx.x;
     const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
     if (u0 >= u1) return;
+    MixLane<BF> ml;
+    ml.init(mat, twL, w, l);
 
-    // DFT matrices (16-bit) and the pass-B output twiddles (FP32), per lane
-    uint2 aA[8];
-#pragma unroll
-    for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
-    const uint4 aD[2] = {mat[MAT_D + l], mat[MAT_D + 64 + l]};
-    typename HF::TwReg twc[4][2][2];
-#pragma unroll
-    for (int gam = 0; gam < 4; ++gam)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
-                const c32 f = twL[(j * col) & (L - 1)];        // exp(-2 pi i j k1 / L)
-                twc[gam][h][i] = HF::to_tw(f.re, -f.im);
-            }
-
-    // Items run as a software pipeline over the two exchange buffers: after
-    // pass B of item u (cc -> bb) and a barrier, pass C of item u (reads bb)
-    // and pass A of item u + 1 (writes cc) run interleaved in one phase, so
-    // the matrix products of one overlap the vector work of the other.
     int64_t s = u0 / M;                // segment and template of item u
     int t = (int)(u0 - s * M);
     int64_t sa = s;                    // segment and template of the pass-A item
     int ta = t;
     uint4 Hn[4];                       // template spectra of the pass-A item
-    auto load_h = [&](int tt) {
-        const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)tt * L) + tau * 4;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
-    };
     typename HF::XReg X[16];           // sigma-scaled spectrum of segment sa at zq(w, l, v)
-    auto load_x = [&](int64_t ss) {
-        const float4 *src = Xs + ss * (L / 2) + tau;
-#pragma unroll
-        for (int vp = 0; vp < 8; ++vp) {
-            const float4 f = src[vp * T];
-            X[2 * vp] = HF::to_x(f.x, f.y);
-            X[2 * vp + 1] = HF::to_x(f.z, f.w);
-        }
-    };
-    // pass A, column set r = 8w + gam: Z = X H rounded once, radix 8 over s
-    // (twiddle folded into the matrix); returns c[2g + c][col][r] packed
-    auto pass_a = [&](int gam, uint32_t &c0, uint32_t &c1) {
-        const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
-        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
-        const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
-        c0 = HF::pack(d[0], d[1]);
-        c1 = HF::pack(d[2], d[3]);
-    };
-    auto store_a = [&](const uint32_t (&pa)[2][8]) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-                *reinterpret_cast<uint4 *>(ccw + 16 * c + 4 * a) =
-                    make_uint4(pa[c][4 * a], pa[c][4 * a + 1], pa[c][4 * a + 2], pa[c][4 * a + 3]);
-    };
     // advance the pass-A item; its template spectra are in flight from here on
     auto next_a = [&]() {
         if (++ta == M) { ta = 0; ++sa; }
-        load_h(ta);
+        load_h16(H16, ta, tau, Hn);
     };
 
-    load_h(ta);
-    load_x(sa);
+    load_h16(H16, ta, tau, Hn);
+    load_x16<BF>(Xs, sa, tau, X);
     float pscale = ps[s];              // 2^-2(e_s + eh) of the pass-A segment
     {
         uint32_t pa[2][8];
 #pragma unroll
-        for (int gam = 0; gam < 8; ++gam) pass_a(gam, pa[0][gam], pa[1][gam]);
+        for (int gam = 0; gam < 8; ++gam) ml.pass_a(X, Hn, gam, pa[0][gam], pa[1][gam]);
         next_a();
-        store_a(pa);
+        xb.store_a(pa);
     }
     // Drain the prologue's loads here (matrices, twiddles, first spectra):
     // a load still outstanding at the loop entry would otherwise leave a
@@ -388,32 +476,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     for (int64_t u = u0; u < u1; ++u) {
-        // ---- pass B of item u: radix 16 over r, then the twiddle W2048^(j k1) ----
-        uint32_t pb[2][2][4];          // [h][i][gam]
-#pragma unroll
-        for (int gam = 0; gam < 4; ++gam) {
-            const uint4 bop = *reinterpret_cast<const uint4 *>(ccr + 16 * gam);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    pb[h][i][gam] = HF::twmul(d[2 * i], d[2 * i + 1], twc[gam][h][i]);
-                }
-            }
-        }
-        // b[col][j], j = 4w + gam + 8 (8h + 2g + i): four consecutive j per store
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                *reinterpret_cast<uint4 *>(bbw + (16 * h + 2 * i) * BJ) =
-                    make_uint4(pb[h][i][0], pb[h][i][1], pb[h][i][2], pb[h][i][3]);
+        ml.pass_b(xb.ccr, xb.bbw);
         // the pass-A item u + 1 may start a new segment (past the last item
         // pass A runs on stale data and its result is never read)
         const float pscale_u = pscale;
         if (sa != s && u + 1 < u1) {
-            load_x(sa);
+            load_x16<BF>(Xs, sa, tau, X);
             pscale = ps[sa];
         }
         __syncthreads();
@@ -431,19 +499,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
         uint32_t pa[2][8];
 #pragma unroll
         for (int gam = 0; gam < 4; ++gam) {
-            pass_a(2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
-            const uint32_t *src = bbr + 4 * gam * BJ;     // j = 16 (4w + gam) + col
-            const uint4 bop = make_uint4(src[0], src[4], src[8], src[12]);
-            pass_a(2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
+            ml.pass_a(X, Hn, 2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
+            const uint4 bop = ml.pass_c_operand(xb.bbr, gam);
+            ml.pass_a(X, Hn, 2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+                const f4v d = ml.pass_c(h, bop);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    // output n = j + 128 m, m = 8 h + 2 g + i
+                for (int i = 0; i < 2; ++i)      // output n = j + 128 m, m = 8 h + 2 g + i
                     otw[(8 * h + 2 * g + i) * OT_ROW + 16 * gam + col] =
                         (d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale_u;
-                }
             }
         }
         // 16 rows of 64 consecutive outputs per wave (the wave's own region:
@@ -454,7 +519,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(otw[m * OT_ROW + l]), rs, off0 + 512 * m, 0,
                                                   kNonTemporal);
         next_a();
-        store_a(pa);
+        xb.store_a(pa);
         __syncthreads();
         if (++t == M) { t = 0; ++s; }
     }
@@ -472,70 +537,12 @@ __global__ __launch_bounds__(128) void mixed_fwd_batch_kernel(BatchSet bs, int M
                                                               int D, int V, int eh, float4 *__restrict__ Xs,
                                                               float *__restrict__ ps)
 {
-    using SG = Seg<2048>;
-    using HF = Half<BF>;
-    constexpr int L = mix::L, T = mix::T;
-    __shared__ c32 lds[2 * SG::LDS_ELEMS];
-    __shared__ float s_max[2];
-    c32 *bufA = lds, *bufC = lds + SG::LDS_ELEMS;
-    const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
     const int64_t sg = blockIdx.x;
     int a = 0;
     while (bs.item_begin[a + 1] <= sg * M) ++a;        // uniform: at most 128 steps
-    const int64_t n = bs.n[a];
     const int64_t base = (sg - bs.item_begin[a] / M) * V - D;
-    const uint32_t *x16 = reinterpret_cast<const uint32_t *>(bs.x[a]);
-
-    c32 v[16];
-    {
-        const uint32_t *xs = x16 + base;
-        const int lo = (int)max<int64_t>(0, -base), hi = (int)min<int64_t>(L, n - base);
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int j = tau + T * m;
-            v[m] = (j >= lo && j < hi) ? HF::unpack(xs[j]) : mk(0.f, 0.f);
-        }
-    }
-    {
-        c32 tw0[16], tw1[16];
-        SG::twiddles(tau, twL, tw0, tw1);
-        SG::fwd0(tau, v, tw0);
-        SG::put_a(tau, v, bufA);
-        __syncthreads();
-        SG::fwd1(tau, v, bufA, tw1);
-    }
-    SG::put_c(tau, v, bufC);
-    __syncthreads();
-    SG::fwd2(tau, v, bufC);
-    __syncthreads();
-    float mx = 0.f;
-    {
-        c32 *dst = lds + SG::k1_of(tau) + 34 * SG::p_of(tau);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            dst[17 * (e >> 3) + 272 * (e & 7)] = v[e];
-            mx = fmaxf(mx, fmaxf(fabsf(v[e].re), fabsf(v[e].im)));
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-    if (l == 0) s_max[w] = mx;
-    __syncthreads();
-    mx = fmaxf(s_max[0], s_max[1]);
-    int es = 0;
-    if (mx > 0.f) {
-        int ex;
-        frexpf(2.f * mx, &ex);
-        es = 4 - ex;
-    }
-    const float sigma = ldexpf(1.f, es);
-    if (tau == 0) ps[sg] = ldexpf(1.f, -2 * (es + eh));
-    const c32 *src = lds + col + 136 * w + 544 * g;
-    float4 *out = Xs + sg * (L / 2) + tau;
-#pragma unroll
-    for (int vp = 0; vp < 8; ++vp) {
-        const c32 z0 = src[17 * vp], z1 = src[17 * vp + 272];
-        out[vp * T] = make_float4(z0.re * sigma, z0.im * sigma, z1.re * sigma, z1.im * sigma);
-    }
+    forward_scaled<BF>(reinterpret_cast<const uint32_t *>(bs.x[a]), bs.n[a], base, twL, eh,
+                       Xs + sg * (mix::L / 2), ps + sg);
 }
 
 // The template loop of fdfir_mixed_kernel over the items of a batch, with
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
     Cand *__restrict__ stage, int2 *__restrict__ hdr, int *__restrict__ nslots, int max_slots)
 {
     using HF = Half<BF>;
-    constexpr int L = mix::L, T = mix::T, BJ = mix::BJ;
+    constexpr int L = mix::L, T = mix::T;
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     // the B->C exchange, and after pass C the candidate list (up to L cells)
     __shared__ __align__(16) uint32_t bx[2 * L];
@@ -561,14 +568,10 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
     __shared__ float smax[T];
     __shared__ int s_cnt;
     __shared__ float s_thr;
-    uint32_t *bb = bx;
     float2 *cand = reinterpret_cast<float2 *>(bx);
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
-    uint32_t *const ccw = cc + mix::cc_word(2 * g, col, 8 * w);
-    const uint32_t *const ccr = cc + mix::cc_word(4 * w, col, 4 * g);
-    uint32_t *const bbw = bb + mix::bb_word(4 * w + 16 * g, col);
-    const uint32_t *const bbr = bb + mix::bb_word(64 * w + col, 4 * g);
+    const MixBases xb(cc, bx, w, l);
     const int nbase = 64 * w + col + 256 * g;     // bin of this lane's value (gam, h, i) = 0 within a segment
     const int64_t nb = gridDim.x, b = blockIdx.x;
     const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
@@ -576,25 +579,11 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
         if (tau == 0) nslots[b] = 0;
         return;
     }
-
-    uint2 aA[8];
-#pragma unroll
-    for (int gam = 0; gam < 8; ++gam) aA[gam] = reinterpret_cast<const uint2 *>(mat)[(8 * w + gam) * 64 + l];
-    const uint4 aD[2] = {mat[MAT_D + l], mat[MAT_D + 64 + l]};
-    typename HF::TwReg twc[4][2][2];
-#pragma unroll
-    for (int gam = 0; gam < 4; ++gam)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
-                const c32 f = twL[(j * col) & (L - 1)];
-                twc[gam][h][i] = HF::to_tw(f.re, -f.im);
-            }
+    MixLane<BF> ml;
+    ml.init(mat, twL, w, l);
 
     // item u: global segment gs = u / M, template t; array a; its segments
-    // start at global segment seg0
+    // are the global segments [seg0, seg1)
     int64_t gs = u0 / M;
     int t = (int)(u0 - gs * M);
     int a = 0;
@@ -604,39 +593,10 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
     int64_t gsa = gs;
     int ta = t;
     uint4 Hn[4];
-    auto load_h = [&](int tt) {
-        const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)tt * L) + tau * 4;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
-    };
     typename HF::XReg X[16];
-    auto load_x = [&](int64_t ss) {
-        const float4 *src = Xs + ss * (L / 2) + tau;
-#pragma unroll
-        for (int vp = 0; vp < 8; ++vp) {
-            const float4 f = src[vp * T];
-            X[2 * vp] = HF::to_x(f.x, f.y);
-            X[2 * vp + 1] = HF::to_x(f.z, f.w);
-        }
-    };
-    auto pass_a = [&](int gam, uint32_t &c0, uint32_t &c1) {
-        const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
-        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
-        const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
-        c0 = HF::pack(d[0], d[1]);
-        c1 = HF::pack(d[2], d[3]);
-    };
-    auto store_a = [&](const uint32_t (&pa)[2][8]) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int aa = 0; aa < 2; ++aa)
-                *reinterpret_cast<uint4 *>(ccw + 16 * c + 4 * aa) =
-                    make_uint4(pa[c][4 * aa], pa[c][4 * aa + 1], pa[c][4 * aa + 2], pa[c][4 * aa + 3]);
-    };
     auto next_a = [&]() {
         if (++ta == M) { ta = 0; ++gsa; }
-        load_h(ta);
+        load_h16(H16, ta, tau, Hn);
     };
 
     int par = 0, kc = 0, slot = 0;
@@ -657,42 +617,23 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
     };
 
     if (tau == 0) s_cnt = 0;
-    load_h(ta);
-    load_x(gsa);
+    load_h16(H16, ta, tau, Hn);
+    load_x16<BF>(Xs, gsa, tau, X);
     float pscale = ps[gs];
     {
         uint32_t pa[2][8];
 #pragma unroll
-        for (int gam = 0; gam < 8; ++gam) pass_a(gam, pa[0][gam], pa[1][gam]);
+        for (int gam = 0; gam < 8; ++gam) ml.pass_a(X, Hn, gam, pa[0][gam], pa[1][gam]);
         next_a();
-        store_a(pa);
+        xb.store_a(pa);
     }
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     for (int64_t u = u0; u < u1; ++u) {
-        // ---- pass B of item u ----
-        uint32_t pb[2][2][4];
-#pragma unroll
-        for (int gam = 0; gam < 4; ++gam) {
-            const uint4 bop = *reinterpret_cast<const uint4 *>(ccr + 16 * gam);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    pb[h][i][gam] = HF::twmul(d[2 * i], d[2 * i + 1], twc[gam][h][i]);
-                }
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                *reinterpret_cast<uint4 *>(bbw + (16 * h + 2 * i) * BJ) =
-                    make_uint4(pb[h][i][0], pb[h][i][1], pb[h][i][2], pb[h][i][3]);
+        ml.pass_b(xb.ccr, xb.bbw);
         const float pscale_u = pscale;
         if (gsa != gs && u + 1 < u1) {
-            load_x(gsa);
+            load_x16<BF>(Xs, gsa, tau, X);
             pscale = ps[gsa];
         }
         __syncthreads();
@@ -703,13 +644,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
         uint32_t pa[2][8];
 #pragma unroll
         for (int gam = 0; gam < 4; ++gam) {
-            pass_a(2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
-            const uint32_t *src = bbr + 4 * gam * BJ;
-            const uint4 bop = make_uint4(src[0], src[4], src[8], src[12]);
-            pass_a(2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
+            ml.pass_a(X, Hn, 2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
+            const uint4 bop = ml.pass_c_operand(xb.bbr, gam);
+            ml.pass_a(X, Hn, 2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const f4v d = HF::mma32(aD[h], bop, f4v{0.f, 0.f, 0.f, 0.f});
+                const f4v d = ml.pass_c(h, bop);
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     const int nn = nbase + 16 * gam + 1024 * h + 128 * i;
@@ -719,7 +659,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
             }
         }
         next_a();
-        store_a(pa);
+        xb.store_a(pa);
         // ---- top-K of item u's cells, merged into the workgroup's list ----
         float mx = -1.f;
 #pragma unroll
@@ -751,7 +691,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int i = 0; i < 2; ++i) any |= (pw[gam][h][i] >= 0.f && pw[gam][h][i] >= th);
-        // (also the barrier after pass C's reads of bb and pass A's writes of cc)
+        // (also the barrier after pass C's reads of bx and pass A's writes of cc)
         if (__syncthreads_or(any)) {
 #pragma unroll
             for (int gam = 0; gam < 4; ++gam)

@@ -67,7 +67,6 @@ FDAS_HD int zq(int w, int l, int v)
 // `out` in each pass.
 FDAS_HD double turns_A(int r, int p, int s) { return (double)((16 * p * s + p * r) & 127) / 128.0; }
 FDAS_HD double turns_D16(int out, int in) { return (double)((out * in) & 15) / 16.0; }
-FDAS_HD double turns_tw(int j, int k1) { return (double)((j * k1) & (L - 1)) / (double)L; }
 
 // Real matrix entry for interleaved rows (2 out + a) and columns (2 in + c)
 // of the complex weight exp(2 pi i turns): [[cos, -sin], [sin, cos]].
