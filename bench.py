@@ -14,6 +14,7 @@ figure for the sampled rows).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -90,6 +91,67 @@ def time_calls(torch, fn, steps, warmup):
     return start.elapsed_time(stop) / steps
 
 
+def time_steps(torch, fn, steps, warmup):
+    """Mean ms per call over `steps` back-to-back calls bracketed by
+    synchronisations, and the per-call times (events between calls)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps, per
+
+
+def percentiles(xs):
+    ys = sorted(xs)
+    pick = lambda q: ys[min(len(ys) - 1, int(round(q * (len(ys) - 1))))]   # noqa: E731
+    return {"p10": pick(0.1), "median": pick(0.5), "p90": pick(0.9)}
+
+
+def mall_evicted_ms(torch, fn, reps=5):
+    """Each call timed alone after writing a 512 MB buffer, so the input and
+    the template spectra are no longer in the 256 MB MALL."""
+    junk = torch.empty(128 << 20, dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    out = []
+    for r in range(reps):
+        junk.fill_(float(r))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    del junk
+    return percentiles(out)
+
+
+def copy_probe_gbs(torch):
+    """Achievable HBM bandwidth: a plain 1 GiB device-to-device copy."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    ms = time_calls(torch, lambda: dst.copy_(src), 5, 2)
+    del src, dst
+    return 2 * 2 ** 30 / ms / 1e6
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_leg(w, P_gpu_rows_fn, target_s: float):
     """FP64 oracle on all 85 templates over a prefix of the outputs, sized to
     take about target_s of wall time on the host's cores."""
@@ -110,11 +172,19 @@ def cpu_baseline_leg(w, P_gpu_rows_fn, target_s: float):
     wall = time.perf_counter() - t0
     st = PlaneStats()
     st.add(list(range(m)), P_gpu_rows_fn(n_s), ref)
+    # the toy workload (9 x 2^16) on one core, for scale
+    from paper_1805_12280_amd import datagen
+    toy = datagen.toy_workload()
+    t0 = time.perf_counter()
+    oracle.power(toy.x, toy.bank.taps, toy.bank.tap_len, nthreads=1)
+    toy_s = time.perf_counter() - t0
     del np
     return {
         "value": m * n_s / wall, "unit": "template-samples/s", "cores": threads, "kind": "oracle",
         "sample": f"all {m} templates x first {n_s} of {w.n} outputs (FP64 direct, C + OpenMP), "
                   f"{wall:.1f} s wall",
+        "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+        "toy_9x2^16_single_core_s": toy_s,
     }, {"rows": m, "outputs": n_s, "norm_err": st.norm_err, "rrmse": st.rrmse}
 
 
@@ -193,6 +263,7 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4, precisi
     probs = [p for _, p in SERVED_LENGTHS]
     ex = GpuExecutor(banks, input_len=1 << 22, topk=16, slots=3, precision=precision,
                      seg_fft={k: (1024 if precision == "fp32" else 2048) for k in banks})
+    ex.reserve(16, max(lens))
     mfree, _ = torch.cuda.mem_get_info()
     budget = int(0.25 * mfree)
 
@@ -205,6 +276,17 @@ def served_leg(torch, jobs_per_rate=240, rates=(0.5, 0.8, 0.95), seed=4, precisi
         return out
 
     def run(spec, gaps):
+        # the host loop runs with Python's cyclic collector paused (collected
+        # just before): a full collection inside a run stalled one scheduler
+        # step by ~40 ms
+        gc.collect()
+        gc.disable()
+        try:
+            return run_inner(spec, gaps)
+        finally:
+            gc.enable()
+
+    def run_inner(spec, gaps):
         sched = Scheduler(ex, budget, max_batch=16, max_wait_s=2e-3)
         t = time.perf_counter()
         jobs = []
@@ -363,7 +445,7 @@ def main():
     torch.cuda.synchronize()
     log(f"plan: {plan.info.as_dict()} variant={plan.variant}")
 
-    ms = time_calls(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup)
+    ms, per_step = time_steps(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup)
     value = m * n / (ms * 1e-3)
     abytes = algorithmic_bytes(n, m, L)
     achieved = abytes / (ms * 1e-3) / 1e9
@@ -397,7 +479,13 @@ def main():
         "hbm_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": abytes,
                          "traffic": traffic},
+        "step_ms": percentiles(per_step),
     }
+    result["mall_evicted_ms"] = mall_evicted_ms(torch, lambda: plan.convolve(x, out=out))
+    cp = copy_probe_gbs(torch)
+    result["hbm_roofline"].update({"copy_probe_gbs": cp, "frac_of_copy_probe": achieved / cp})
+    log(f"per step {result['step_ms']}, MALL evicted {result['mall_evicted_ms']}, "
+        f"copy probe {cp:.0f} GB/s")
 
     if not args.no_tdfir:
         td_steps = max(2, min(args.steps, 5))
