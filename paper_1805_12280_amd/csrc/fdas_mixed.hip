@@ -432,12 +432,14 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     constexpr int L = mix::L;
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
-    // per-wave transpose of the powers: a wave's pass C yields outputs
+    // Per-wave transpose of the powers: a wave's pass C yields outputs
     // n = 64 w + j' + 128 m (j' < 64, m < 16) with 16 consecutive j' per lane
-    // group; staged as [m][j'] (row pitch OT_ROW) they are stored back as 16
-    // rows of 64 consecutive floats
-    constexpr int OT_ROW = 72;      // 64 + 8: the four lane groups (rows 2 apart) hit distinct banks
-    __shared__ float ot[2][16 * OT_ROW];
+    // group; staged as rows of 64 (pitch OT_ROW) they are stored back as 16
+    // rows of 64 consecutive floats.  The staging reuses the wave's own rows
+    // of bb (its pass-C operands, 16 x BJ words, dead once read), with
+    // output row m at row 4 g + 2 h + i (m = 8 h + 2 g + i), which puts the
+    // four lane groups 16 banks apart.
+    constexpr int OT_ROW = mix::BJ;
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
     const MixBases xb(cc, bb, w, l);
@@ -495,28 +497,32 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
         const int64_t base = s * V - D;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             P + (int64_t)t * ld + s * V, 0, 4 * ((int)min<int64_t>(L, n - base) - D), kBufWord3);
-        float *const otw = ot[w];
+        float *const otw = reinterpret_cast<float *>(bb) + 16 * w * mix::BJ;
         uint32_t pa[2][8];
+        uint4 bops[4];
+#pragma unroll
+        for (int gam = 0; gam < 4; ++gam) bops[gam] = ml.pass_c_operand(xb.bbr, gam);
 #pragma unroll
         for (int gam = 0; gam < 4; ++gam) {
             ml.pass_a(X, Hn, 2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
-            const uint4 bop = ml.pass_c_operand(xb.bbr, gam);
             ml.pass_a(X, Hn, 2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const f4v d = ml.pass_c(h, bop);
+                const f4v d = ml.pass_c(h, bops[gam]);
 #pragma unroll
-                for (int i = 0; i < 2; ++i)      // output n = j + 128 m, m = 8 h + 2 g + i
-                    otw[(8 * h + 2 * g + i) * OT_ROW + 16 * gam + col] =
+                for (int i = 0; i < 2; ++i)      // output n = j + 128 m, m = 8 h + 2 g + i, row 4 g + 2 h + i
+                    otw[(4 * g + 2 * h + i) * OT_ROW + 16 * gam + col] =
                         (d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale_u;
             }
         }
         // 16 rows of 64 consecutive outputs per wave (the wave's own region:
-        // its LDS accesses are executed in order, no barrier needed)
+        // its LDS accesses are executed in order, so its pass-C reads above
+        // are done before these rows are overwritten; no barrier needed)
         const int off0 = 4 * (64 * w + l - D);
 #pragma unroll
         for (int m = 0; m < 16; ++m)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(otw[m * OT_ROW + l]), rs, off0 + 512 * m, 0,
+            __builtin_amdgcn_raw_buffer_store_b32(
+                __float_as_uint(otw[(4 * ((m >> 1) & 3) + 2 * (m >> 3) + (m & 1)) * OT_ROW + l]), rs, off0 + 512 * m, 0,
                                                   kNonTemporal);
         next_a();
         xb.store_a(pa);
