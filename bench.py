@@ -197,9 +197,10 @@ def batched_leg(torch, fdas, steps, warmup):
     batch = datagen.dm_trial_batch()
     bank = batch.bank
     dev = [torch.from_numpy(x).to("cuda:0") for x in batch.xs]
-    best, tuned = autotune.tune(bank, dev, mode="batched", topk=16, use_cache=False)
-    log(f"autotune (ms per batch): {tuned} -> L = {best}")
+    best, wg, tuned = autotune.tune(bank, dev, mode="batched", topk=16, use_cache=False)
+    log(f"autotune (ms per batch, L/workgroups per CU): {tuned} -> L = {best}, wg = {wg}")
     plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(batch.lengths), seg_fft=best)
+    plan.set_workgroups_per_cu(wg)
     ws = torch.empty(plan.batched_workspace_bytes(batch.lengths, 16), dtype=torch.uint8, device="cuda:0")
     out = torch.empty((len(dev), 16, 3), dtype=torch.int32, device="cuda:0")
     side = torch.cuda.Stream()
@@ -214,7 +215,7 @@ def batched_leg(torch, fdas, steps, warmup):
     tflops = flops / (ms * 1e-3) / 1e12
     plan.close()
     res = {"workload": batch.name, "arrays": len(dev), "points": sum(batch.lengths),
-           "topk": 16, "seg_fft": best, "autotune_ms": tuned, "graph": True,
+           "topk": 16, "seg_fft": best, "workgroups_per_cu": wg, "autotune_ms": tuned, "graph": True,
            "ms_per_step": ms, "value": samples / (ms * 1e-3), "unit": "template-samples/s",
            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
@@ -438,9 +439,11 @@ def main():
         L = args.seg_fft
     else:
         from paper_1805_12280_amd import autotune
-        L, tuned = autotune.tune(w.bank, [x], mode="plane", use_cache=False)
-        log(f"autotune (ms per call): {tuned} -> L = {L}")
+        L, wg, tuned = autotune.tune(w.bank, [x], mode="plane", use_cache=False)
+        log(f"autotune (ms per call, L/workgroups per CU, 0 = full grid): {tuned} -> L = {L}, wg = {wg}")
     plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=L)
+    if not args.seg_fft:
+        plan.set_workgroups_per_cu(wg)
     out = torch.empty((m, n), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log(f"plan: {plan.info.as_dict()} variant={plan.variant}")
@@ -468,7 +471,8 @@ def main():
         "data": "synthetic (seeded complex Gaussian noise + 3 chirps at amplitude-SNR 8; "
                 "85 chirp templates z=-42..42)",
         "config": {"workload": w.name, "templates": m, "n": n, "k_max": k_max,
-                   "taps_total": int(w.bank.tap_len.sum()), "seg_fft": L, "autotune_ms": tuned,
+                   "taps_total": int(w.bank.tap_len.sum()), "seg_fft": L,
+                   "workgroups_per_cu": plan.info.wg_per_cu, "autotune_ms": tuned,
                    "path": "overlap-save FDFIR + |y|^2, one fused launch"},
         # the fused kernel is bound by VALU issue (counters: ~0.9 of one wave64
         # VALU instruction per CU per cycle), so its roofline is the FP32 vector

@@ -73,6 +73,8 @@ typedef struct {
     int32_t fused_grid;       /* workgroups of one fdas_convolve launch at input_len */
     int32_t variant;          /* kernel variant id (see fdas_variant_name) */
     int32_t device;           /* HIP device ordinal the plan lives on */
+    int32_t wg_per_cu_max;    /* persistent workgroups per CU that fit (fused launch) */
+    int32_t wg_per_cu;        /* the cap in force (fdas_plan_set_workgroups_per_cu), 0 = none */
 } fdas_plan_info_t;
 
 /*
@@ -119,6 +121,20 @@ typedef struct {
 int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *tap_len,
                      int32_t M, int32_t K_max, int64_t input_len, int32_t seg_fft,
                      uint32_t flags, void *hip_stream);
+
+/*
+ * fdas_plan_set_workgroups_per_cu -- size of the persistent grids.
+ *
+ * fdas_convolve and fdas_convolve_batched launch one persistent grid that
+ * gives each workgroup a contiguous range of (segment, template) items
+ * (Alg. 2's loops over segments and filters).  By default the grid holds as
+ * many workgroups per compute unit as fit; per_cu >= 1 caps that number
+ * (a tuning knob: fewer, longer-lived workgroups share each segment's
+ * forward transform over more templates).  per_cu = 0 removes the cap.
+ * Not to be called while calls on the plan may be enqueued from other host
+ * threads.  Errors: FDAS_EINVAL (NULL plan, per_cu < 0).
+ */
+int fdas_plan_set_workgroups_per_cu(fdas_plan *plan, int32_t per_cu);
 
 /*
  * fdas_convolve -- the overlap-save FDFIR hot path (Alg. 2 with the power

@@ -1,13 +1,15 @@
-"""Segment-length autotuner for the FT-convolution plans.
+"""Segment-length and grid autotuner for the FT-convolution plans.
 
 The segment transform length L trades the overlap discarded per segment
 (D / L, Section 3.2.2) against the transform cost per point (log2 L); the
 paper finds the best N_FT experimentally per device (Section 3.3, Fig. 7/8).
-Here every admissible L in {1024, 2048, 4096} (K_max <= L/2) is timed on the
-device with the call shape that will be used (plane or batched top-K), and
-the fastest is kept.  Results are cached in a JSON file keyed by the device
-name, bank shape and length profile, so a server or bench pays the search
-once per device and bank.
+The persistent grid's size (workgroups per CU) trades latency hiding against
+how many templates share each forward transform.  Here every admissible L in
+{1024, 2048, 4096} (K_max <= L/2), each with the full and the half grid, is
+timed on the device with the call shape that will be used (plane or batched
+top-K), and the fastest pair is kept.  Results are cached in a JSON file
+keyed by the device name, bank shape and length profile, so a server or
+bench pays the search once per device and bank.
 """
 from __future__ import annotations
 
@@ -65,40 +67,48 @@ def _time(torch, fn, reps):
 
 def tune(bank, arrays, mode: str = "batched", topk: int = 16, reps: int = 3,
          use_cache: bool = True, candidates=CANDIDATES):
-    """Pick L for `bank` on the current GPU.
+    """Pick (L, workgroups per CU) for `bank` on the current GPU.
 
     arrays: CUDA complex64 tensors shaped like the real inputs (their values
     do not matter).  mode: "batched" (top-K over the list) or "plane" (the
-    first array's full power plane).  Returns (best_L, {L: ms}).
+    first array's full power plane).  Returns (best_L, best_wg, {"L/wg": ms})
+    with best_wg = 0 meaning the full grid (pass it to
+    Plan.set_workgroups_per_cu).
     """
     import torch
     path = cache_path()
     key = _key(torch, bank, [a.shape[0] for a in arrays], mode, topk)
     cache = _load_cache(path) if use_cache else {}
-    if use_cache and key in cache:
+    if use_cache and key in cache and "wg" in cache[key]:
         ent = cache[key]
-        return int(ent["best"]), {int(k): v for k, v in ent["ms"].items()}
+        return int(ent["best"]), int(ent["wg"]), dict(ent["ms"])
     n_max = max(a.shape[0] for a in arrays)
     times = {}
+    best = None
     for L in candidates:
         if bank.k_max > L // 2:
             continue
         plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n_max, seg_fft=L)
-        if mode == "batched":
-            ws = torch.empty(plan.batched_workspace_bytes([a.shape[0] for a in arrays], topk),
-                             dtype=torch.uint8, device=arrays[0].device)
-            out = torch.empty((len(arrays), topk, 3), dtype=torch.int32, device=arrays[0].device)
-            fn = lambda: plan.convolve_batched(arrays, topk=topk, out=out, workspace=ws)   # noqa: E731
-        else:
-            x = arrays[0]
-            out = torch.empty((bank.num_templates, x.shape[0]), dtype=torch.float32, device=x.device)
-            fn = lambda: plan.convolve(x, out=out)   # noqa: E731
-        times[L] = _time(torch, fn, reps)
+        full = plan.info.wg_per_cu_max
+        for wg in sorted({0, max(1, full // 2)}):
+            plan.set_workgroups_per_cu(wg)
+            if mode == "batched":
+                ws = torch.empty(plan.batched_workspace_bytes([a.shape[0] for a in arrays], topk),
+                                 dtype=torch.uint8, device=arrays[0].device)
+                out = torch.empty((len(arrays), topk, 3), dtype=torch.int32, device=arrays[0].device)
+                fn = lambda: plan.convolve_batched(arrays, topk=topk, out=out, workspace=ws)   # noqa: E731
+            else:
+                x = arrays[0]
+                out = torch.empty((bank.num_templates, x.shape[0]), dtype=torch.float32, device=x.device)
+                fn = lambda: plan.convolve(x, out=out)   # noqa: E731
+            ms = _time(torch, fn, reps)
+            times[f"{L}/{wg}"] = ms
+            if best is None or ms < best[2]:
+                best = (L, wg, ms)
         plan.close()
-    if not times:
+    if best is None:
         raise fdas.FdasError(fdas.FDAS_EINVAL, "no segment length admits this bank")
-    best = min(times, key=times.get)
     if use_cache:
-        cache[key] = {"best": best, "ms": times, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+        cache[key] = {"best": best[0], "wg": best[1], "ms": times, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
         _store_cache(path, cache)
-    return best, times
+    return best[0], best[1], times

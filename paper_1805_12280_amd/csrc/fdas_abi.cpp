@@ -72,6 +72,7 @@ struct fdas_plan {
     int prec = 0;              // 0 float32, 1 binary16, 2 bfloat16
     int mixed_per_cu = 1;
     int mixed_topk_per_cu = 1;
+    int wg_cap = 0;            // fdas_plan_set_workgroups_per_cu, 0 = none
     int eh = 0;                // template spectra scaled by 2^eh in 16-bit storage
     uint32_t *d_H16 = nullptr; // [M][2048] packed 16-bit pairs, pass-A lane order
     void *d_mat = nullptr;     // 16-bit DFT matrices of the inverse passes
@@ -251,9 +252,12 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
 
 namespace {
 
+// persistent workgroups per CU: what fits, capped by the plan's setting
+int per_cu(const fdas_plan *p, int fit) { return p->wg_cap > 0 ? std::min(fit, p->wg_cap) : fit; }
+
 int64_t fused_grid(const fdas_plan *p, int64_t items)
 {
-    const int64_t resident = (int64_t)p->fused_per_cu * std::max(1, p->num_cu);
+    const int64_t resident = (int64_t)per_cu(p, p->fused_per_cu) * std::max(1, p->num_cu);
     return std::max<int64_t>(1, std::min(items, resident));
 }
 
@@ -279,7 +283,8 @@ FDAS_API int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, f
         m.bf = plan->prec == 2;
         m.segments = (n + plan->V - 1) / plan->V;
         m.items = m.segments * plan->M;
-        m.grid = std::max<int64_t>(1, std::min<int64_t>(m.items, (int64_t)plan->mixed_per_cu * std::max(1, plan->num_cu)));
+        m.grid = std::max<int64_t>(1, std::min<int64_t>(m.items, (int64_t)per_cu(plan, plan->mixed_per_cu) *
+                                                                  std::max(1, plan->num_cu)));
         m.stage = plan->d_stage;
         m.P = d_power;
         m.ld = ld_power;
@@ -377,8 +382,8 @@ int batch_shape(const fdas_plan *plan, const int64_t *n, int32_t count, int32_t 
     }
     sh.bs.item_begin[count] = acc;
     sh.items = acc;
-    const int per_cu = plan->prec ? plan->mixed_topk_per_cu : plan->topk_per_cu;
-    const int64_t resident = (int64_t)per_cu * std::max(1, plan->num_cu);
+    const int fit = plan->prec ? plan->mixed_topk_per_cu : plan->topk_per_cu;
+    const int64_t resident = (int64_t)per_cu(plan, fit) * std::max(1, plan->num_cu);
     sh.grid = std::max<int64_t>(1, std::min(acc, resident));
     // most arrays any workgroup's contiguous item range touches
     int ms = 1, a0 = 0;
@@ -518,6 +523,15 @@ FDAS_API int fdas_plan_template_spectra(const fdas_plan *plan, void *host_out)
     return FDAS_OK;
 }
 
+FDAS_API int fdas_plan_set_workgroups_per_cu(fdas_plan *plan, int32_t per_cu_cap)
+{
+    g_last_error.clear();
+    if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    if (per_cu_cap < 0) return fail(FDAS_EINVAL, "per_cu=%d < 0", per_cu_cap);
+    plan->wg_cap = per_cu_cap;
+    return FDAS_OK;
+}
+
 FDAS_API int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out)
 {
     g_last_error.clear();
@@ -534,6 +548,8 @@ FDAS_API int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out)
     out->fused_grid = (int32_t)fused_grid(plan, out->num_segments * plan->M);
     out->variant = plan->prec == 1 ? kVariantMixedFp16 : plan->prec == 2 ? kVariantMixedBf16 : kVariantFusedPersistent;
     out->device = plan->device;
+    out->wg_per_cu_max = plan->prec ? plan->mixed_per_cu : plan->fused_per_cu;
+    out->wg_per_cu = plan->wg_cap;
     return FDAS_OK;
 }
 

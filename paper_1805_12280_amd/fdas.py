@@ -24,7 +24,8 @@ PRECISIONS = {"fp32": FDAS_FP32, "fp16": FDAS_FP16, "bf16": FDAS_BF16}
 MAX_BATCH = 128
 MAX_TOPK = 32
 
-EXPORTED = ("fdas_plan_create", "fdas_convolve", "fdas_tdfir", "fdas_batched_workspace_bytes",
+EXPORTED = ("fdas_plan_create", "fdas_plan_set_workgroups_per_cu", "fdas_convolve", "fdas_tdfir",
+            "fdas_batched_workspace_bytes",
             "fdas_convolve_batched", "fdas_segment_fft",
             "fdas_plan_template_spectra", "fdas_plan_info", "fdas_plan_destroy",
             "fdas_strerror", "fdas_last_error", "fdas_variant_name")
@@ -43,7 +44,8 @@ class PlanInfo(ctypes.Structure):
                 ("num_templates", ctypes.c_int32), ("input_len", ctypes.c_int64),
                 ("resident_bytes", ctypes.c_int64), ("threads_per_fft", ctypes.c_int32),
                 ("fused_grid", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("wg_per_cu_max", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     lib.fdas_segment_fft.restype = ctypes.c_int
     lib.fdas_plan_template_spectra.argtypes = [vp, vp]
     lib.fdas_plan_template_spectra.restype = ctypes.c_int
+    lib.fdas_plan_set_workgroups_per_cu.argtypes = [vp, i32]
+    lib.fdas_plan_set_workgroups_per_cu.restype = ctypes.c_int
     lib.fdas_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.fdas_plan_info.restype = ctypes.c_int
     lib.fdas_plan_destroy.argtypes = [vp]
@@ -185,6 +189,10 @@ class Plan:
     @property
     def variant(self) -> str:
         return self._lib.fdas_variant_name(self.info.variant).decode()
+
+    def set_workgroups_per_cu(self, per_cu: int):
+        """Cap the persistent grids at per_cu workgroups per CU (0: no cap)."""
+        check(self._lib.fdas_plan_set_workgroups_per_cu(self._h, int(per_cu)))
 
     # -- calls --------------------------------------------------------------
     def input_dtype(self):

@@ -124,3 +124,30 @@ def test_template_spectra_against_definition(env, L):
         ref = oracle.template_spectrum(bank.taps[t, : bank.tap_len[t]], L)
         # float64 arithmetic rounded once to float32
         assert np.max(np.abs(H[t] - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_workgroups_per_cu_knob(env, precision):
+    """The persistent grid's size changes which workgroup runs an item, not
+    what it computes: planes and batched candidates are bitwise identical
+    for every cap, and the cap is reported and validated."""
+    torch, fdas, lib = env
+    x, bank = datagen.random_case(61, 50011, 5, 40)
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=x.shape[0], seg_fft=2048, precision=precision)
+    xd = torch.from_numpy(x).cuda()
+    if precision != "fp32":
+        xd = torch.view_as_real(xd).to(torch.float16).contiguous()
+    xs = [xd, xd[:7777].contiguous()]
+    full = plan.info.wg_per_cu_max
+    assert full >= 1 and plan.info.wg_per_cu == 0
+    ref_plane = plan.convolve(xd)
+    ref_cands = plan.convolve_batched(xs, topk=16)
+    for cap in (1, max(1, full // 2), full + 3):
+        plan.set_workgroups_per_cu(cap)
+        assert plan.info.wg_per_cu == cap
+        assert torch.equal(plan.convolve(xd), ref_plane), cap
+        assert torch.equal(plan.convolve_batched(xs, topk=16), ref_cands), cap
+    plan.set_workgroups_per_cu(0)
+    assert lib.fdas_plan_set_workgroups_per_cu(plan._h, -1) == fdas.FDAS_EINVAL
+    assert lib.fdas_plan_set_workgroups_per_cu(None, 1) == fdas.FDAS_EINVAL
+    plan.close()
