@@ -66,9 +66,6 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_topk_kernel(
 
     int par = 0, kc = 0, slot = 0;
     float thr = -1.f;                       // a cell enters the list if P >= thr
-    c32 X[16];
-    int64_t cur_s = -1;
-    int cur_a = -1;
     auto flush = [&](int arr) {
         if (slot < max_slots) {
             Cand *dst = stage + ((int64_t)b * max_slots + slot) * K;
@@ -84,14 +81,16 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_topk_kernel(
         ++slot;
     };
 
-    for (int64_t u = u0; u < u1; ++u) {
+    // Segments outside, that segment's templates inside, so the spectrum X
+    // is invariant in the inner loop (no per-item register copies of it).
+    for (int64_t u = u0; u < u1;) {
         const int64_t n = bs.n[a];
         const int64_t base = s * V - D;
-        if (s != cur_s || a != cur_a) {
-            cur_s = s;
-            cur_a = a;
+        const int hi = (int)min<int64_t>(L, n - base);
+        c32 X[16];
+        {
             const c32 *xs = bs.x[a] + base;
-            const int lo = (int)max<int64_t>(0, -base), hi = (int)min<int64_t>(L, n - base);
+            const int lo = (int)max<int64_t>(0, -base);
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const int j = tau + T * m;
@@ -107,96 +106,98 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_topk_kernel(
             SG::fwd2(tau, X, bufC);
             __syncthreads();
         }
-        c32 v[16];
-        SG::inv2(tau, X, Hn, bufC);
-        const int tn = (t + 1 == M) ? 0 : t + 1;
-        {
-            const c32 *Ht = H + (int64_t)tn * L;
+        const int64_t u_end = min<int64_t>(u1, u + (M - t));     // this segment's items
+        for (; u < u_end; ++u) {
+            c32 v[16];
+            SG::inv2(tau, X, Hn, bufC);
+            const int tn = (t + 1 == M) ? 0 : t + 1;
+            {
+                const c32 *Ht = H + (int64_t)tn * L;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
-        }
-        __syncthreads();
-        SG::inv1(tau, v, bufC, tw1);
-        SG::put_a_inv(tau, v, bufA);
-        __syncthreads();
-        SG::inv0(tau, v, bufA, tw0);
-
-        // ---- top-K of this item's cells, merged into the workgroup's list ----
-        const int hi = (int)min<int64_t>(L, n - base);
-        float pw[16];
-        float mx = -1.f;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int j = tau + T * m;
-            pw[m] = (j >= D && j < hi) ? norm2(v[m]) : -1.f;   // -1: not an output
-            mx = fmaxf(mx, pw[m]);
-        }
-        float th = thr;
-        if (kc < K) {
-            // No full list yet: the K-th largest per-work-item maximum is a
-            // lower bound of this item's K-th largest cell, so no cell of the
-            // true top-K is below it.
-            float *smax = reinterpret_cast<float *>(bufC);      // free until the next inv2
-            smax[tau] = mx;
-            __syncthreads();
-            int gt = 0, ge = 0;
-            for (int q = 0; q < T; ++q) {
-                const float o = smax[q];
-                gt += o > mx;
-                ge += o >= mx;
-            }
-            if (gt < K && ge >= K) s_thr = mx;                   // every writer writes the same value
-            __syncthreads();
-            th = s_thr;
-        }
-        bool any = false;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) any |= (pw[m] >= 0.f && pw[m] >= th);
-        if (__syncthreads_or(any)) {
-            float2 *cand = reinterpret_cast<float2 *>(bufA);    // free: pass 0' reads are done
-#pragma unroll
-            for (int m = 0; m < 16; ++m)
-                if (pw[m] >= 0.f && pw[m] >= th) {
-                    const int c = atomicAdd(&s_cnt, 1);
-                    cand[c] = make_float2(pw[m], __int_as_float(tau + T * m));
-                }
-            __syncthreads();
-            const int cnt = s_cnt;
-            const int total = kc + cnt;
-            for (int e = tau; e < total; e += T) {
-                float pe;
-                int te, ie;
-                if (e < kc) {
-                    pe = keptP[par][e];
-                    te = keptT[par][e];
-                    ie = keptI[par][e];
-                } else {
-                    const float2 c = cand[e - kc];
-                    pe = c.x;
-                    te = t;
-                    ie = (int)(base + __float_as_int(c.y));
-                }
-                int rank = 0;
-                for (int f = 0; f < kc; ++f) rank += beats(keptP[par][f], keptT[par][f], keptI[par][f], pe, te, ie);
-                for (int f = 0; f < cnt; ++f) {
-                    const float2 c = cand[f];
-                    rank += beats(c.x, t, (int)(base + __float_as_int(c.y)), pe, te, ie);
-                }
-                if (rank < K) {
-                    keptP[par ^ 1][rank] = pe;
-                    keptT[par ^ 1][rank] = te;
-                    keptI[par ^ 1][rank] = ie;
-                }
+                for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
             }
             __syncthreads();
-            par ^= 1;
-            kc = min(K, total);
-            thr = kc == K ? keptP[par][K - 1] : -1.f;
-            if (tau == 0) s_cnt = 0;        // read again only after the next item's barriers
-        }
+            SG::inv1(tau, v, bufC, tw1);
+            SG::put_a_inv(tau, v, bufA);
+            __syncthreads();
+            SG::inv0(tau, v, bufA, tw0);
 
-        // ---- next item ----
-        t = tn;
+            // ---- top-K of this item's cells, merged into the workgroup's list ----
+            float pw[16];
+            float mx = -1.f;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int j = tau + T * m;
+                pw[m] = (j >= D && j < hi) ? norm2(v[m]) : -1.f;   // -1: not an output
+                mx = fmaxf(mx, pw[m]);
+            }
+            float th = thr;
+            if (kc < K) {
+                // No full list yet: the K-th largest per-work-item maximum is a
+                // lower bound of this item's K-th largest cell, so no cell of the
+                // true top-K is below it.
+                float *smax = reinterpret_cast<float *>(bufC);      // free until the next inv2
+                smax[tau] = mx;
+                __syncthreads();
+                int gt = 0, ge = 0;
+                for (int q = 0; q < T; ++q) {
+                    const float o = smax[q];
+                    gt += o > mx;
+                    ge += o >= mx;
+                }
+                if (gt < K && ge >= K) s_thr = mx;                   // every writer writes the same value
+                __syncthreads();
+                th = s_thr;
+            }
+            bool any = false;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) any |= (pw[m] >= 0.f && pw[m] >= th);
+            if (__syncthreads_or(any)) {
+                float2 *cand = reinterpret_cast<float2 *>(bufA);    // free: pass 0' reads are done
+#pragma unroll
+                for (int m = 0; m < 16; ++m)
+                    if (pw[m] >= 0.f && pw[m] >= th) {
+                        const int c = atomicAdd(&s_cnt, 1);
+                        cand[c] = make_float2(pw[m], __int_as_float(tau + T * m));
+                    }
+                __syncthreads();
+                const int cnt = s_cnt;
+                const int total = kc + cnt;
+                for (int e = tau; e < total; e += T) {
+                    float pe;
+                    int te, ie;
+                    if (e < kc) {
+                        pe = keptP[par][e];
+                        te = keptT[par][e];
+                        ie = keptI[par][e];
+                    } else {
+                        const float2 c = cand[e - kc];
+                        pe = c.x;
+                        te = t;
+                        ie = (int)(base + __float_as_int(c.y));
+                    }
+                    int rank = 0;
+                    for (int f = 0; f < kc; ++f) rank += beats(keptP[par][f], keptT[par][f], keptI[par][f], pe, te, ie);
+                    for (int f = 0; f < cnt; ++f) {
+                        const float2 c = cand[f];
+                        rank += beats(c.x, t, (int)(base + __float_as_int(c.y)), pe, te, ie);
+                    }
+                    if (rank < K) {
+                        keptP[par ^ 1][rank] = pe;
+                        keptT[par ^ 1][rank] = te;
+                        keptI[par ^ 1][rank] = ie;
+                    }
+                }
+                __syncthreads();
+                par ^= 1;
+                kc = min(K, total);
+                thr = kc == K ? keptP[par][K - 1] : -1.f;
+                if (tau == 0) s_cnt = 0;        // read again only after the next item's barriers
+            }
+
+            t = tn;
+        }
+        // ---- next segment (t wrapped to 0 unless the range ended inside it) ----
         if (t == 0) {
             if (++s == s_end) {
                 flush(a);

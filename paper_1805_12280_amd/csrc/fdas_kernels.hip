@@ -71,6 +71,11 @@ __global__ void tspec_kernel(const c32 *__restrict__ taps, const int *__restrict
 // V = L - D.  Two LDS buffers (one per exchange) need two barriers per
 // inverse transform; the template spectra of the next item are loaded into
 // registers while the current item is transformed.
+//
+// The loops are nested (segments outside, that segment's templates inside)
+// so the spectrum X is invariant in the inner loop: with one flat loop over
+// items and the forward transform under a branch, X is a loop-carried value
+// and the compiler copies its 32 registers twice per item.
 template <int L>
 __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
     const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ H, const c32 *__restrict__ twL,
@@ -96,14 +101,13 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
 #pragma unroll
         for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
     }
-    c32 X[16];
-    int64_t cur = -1;
-    for (int64_t u = u0; u < u1; ++u) {
+    for (int64_t u = u0; u < u1; ++s) {
         const int64_t base = s * V - D;        // input/output index of segment point 0
-        if (s != cur) {
-            cur = s;
+        const int hi = (int)min<int64_t>(L, n - base);
+        c32 X[16];
+        {
             const c32 *xs = x + base;           // uniform; read only inside [0, n)
-            const int lo = (int)max<int64_t>(0, -base), hi = (int)min<int64_t>(L, n - base);
+            const int lo = (int)max<int64_t>(0, -base);
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const int j = tau + T * m;
@@ -119,38 +123,40 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
             SG::fwd2(tau, X, bufC);
             __syncthreads();                    // bufC reads done before inv2 rewrites it
         }
-        c32 v[16];
-        SG::inv2(tau, X, Hn, bufC);
-        // next item's template spectra, in flight during this transform
-        // (after the last item this reads a valid row that is never used)
-        const int tn = (t + 1 == M) ? 0 : t + 1;
-        {
-            const c32 *Ht = H + (int64_t)tn * L;
+        // segment inside the input and the discard within row 0: rows 1..15
+        // are kept whole
+        const bool whole = D <= T && hi == L;
+        const int64_t u_end = min<int64_t>(u1, u + (M - t));     // this segment's items
+        for (; u < u_end; ++u) {
+            c32 v[16];
+            SG::inv2(tau, X, Hn, bufC);
+            // next item's template spectra, in flight during this transform
+            // (after the last item this reads a valid row that is never used)
+            const int tn = (t + 1 == M) ? 0 : t + 1;
+            {
+                const c32 *Ht = H + (int64_t)tn * L;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
-        }
-        __syncthreads();
-        SG::inv1(tau, v, bufC, tw1);
-        SG::put_a_inv(tau, v, bufA);
-        __syncthreads();
-        SG::inv0(tau, v, bufA, tw0);
-        float *Pt = P + (int64_t)t * ld + base;     // uniform; written only at j >= D
-        const int hi = (int)min<int64_t>(L, n - base);
-        if (D <= T && hi == L) {
-            // segment inside the input and the discard within row 0:
-            // rows 1..15 are kept whole
-            if (tau >= D) __builtin_nontemporal_store(norm2(v[0]), Pt + tau);
-#pragma unroll
-            for (int m = 1; m < 16; ++m) __builtin_nontemporal_store(norm2(v[m]), Pt + tau + T * m);
-        } else {
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const int j = tau + T * m;
-                if (j >= D && j < hi) __builtin_nontemporal_store(norm2(v[m]), Pt + j);
+                for (int e = 0; e < 16; ++e) Hn[e] = Ht[e * T + tau];
             }
+            __syncthreads();
+            SG::inv1(tau, v, bufC, tw1);
+            SG::put_a_inv(tau, v, bufA);
+            __syncthreads();
+            SG::inv0(tau, v, bufA, tw0);
+            float *Pt = P + (int64_t)t * ld + base;     // uniform; written only at j >= D
+            if (whole) {
+                if (tau >= D) __builtin_nontemporal_store(norm2(v[0]), Pt + tau);
+#pragma unroll
+                for (int m = 1; m < 16; ++m) __builtin_nontemporal_store(norm2(v[m]), Pt + tau + T * m);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const int j = tau + T * m;
+                    if (j >= D && j < hi) __builtin_nontemporal_store(norm2(v[m]), Pt + j);
+                }
+            }
+            t = tn;
         }
-        t = tn;
-        if (t == 0) ++s;
     }
 }
 
