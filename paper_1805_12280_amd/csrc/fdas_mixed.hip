@@ -39,6 +39,14 @@ template <> struct Half<false> {   // IEEE binary16
         h2v v = {(_Float16)re, (_Float16)im};   // round to nearest even
         return __builtin_bit_cast(uint32_t, v);
     }
+    // the same rounding without the barrier, for matrix-core results (no
+    // arithmetic precedes the conversion, and a barrier on two registers of
+    // one result tuple costs a register copy)
+    __device__ static uint32_t pack_acc(float re, float im)
+    {
+        h2v v = {(_Float16)re, (_Float16)im};
+        return __builtin_bit_cast(uint32_t, v);
+    }
     __device__ static c32 unpack(uint32_t w)
     {
         const h2v v = __builtin_bit_cast(h2v, w);
@@ -71,7 +79,7 @@ template <> struct Half<false> {   // IEEE binary16
     __device__ static XReg to_x(float re, float im) { return pack(re, im); }
     __device__ static TwReg to_tw(float re, float im) { return pack(re, im); }
     __device__ static uint32_t zmul(XReg x, uint32_t h) { return cmulp(x, h); }
-    __device__ static uint32_t twmul(float re, float im, TwReg w) { return cmulp(pack(re, im), w); }
+    __device__ static uint32_t twmul(float re, float im, TwReg w) { return cmulp(pack_acc(re, im), w); }
 };
 
 template <> struct Half<true> {    // bfloat16
@@ -80,6 +88,7 @@ template <> struct Half<true> {    // bfloat16
         b2v v = {(__bf16)re, (__bf16)im};       // round to nearest even
         return __builtin_bit_cast(uint32_t, v);
     }
+    __device__ static uint32_t pack_acc(float re, float im) { return pack(re, im); }
     __device__ static c32 unpack(uint32_t w)
     {
         return mk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
@@ -330,8 +339,8 @@ template <bool BF> struct MixLane {
         const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
         const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
         const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
-        c0 = HF::pack(d[0], d[1]);
-        c1 = HF::pack(d[2], d[3]);
+        c0 = HF::pack_acc(d[0], d[1]);
+        c1 = HF::pack_acc(d[2], d[3]);
     }
     // pass B: radix 16 over r for p = 4w + gam (reads cc), the twiddle, and
     // b[col][j], j = 4w + gam + 8 (8h + 2g + i), four consecutive j per store
