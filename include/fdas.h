@@ -167,7 +167,12 @@ int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, float *d_p
 /*
  * fdas_tdfir -- direct time-domain FIR (Section 3.1, Eq. (1)), taps taken in
  * blocks and accumulated (overlap-add on the taps, Alg. 1), with the same
- * power output.  Arguments, output contract and errors as fdas_convolve.
+ * power output.  Arguments, output contract and errors as fdas_convolve;
+ * float32 plans only (FDAS_EUNSUPPORTED otherwise).  Its workgroups hold an
+ * input tile and the taps of a few templates in LDS, about
+ * 9 * (2048 + K_max) + max(4096, 8 * K_max) bytes; a K_max for which that
+ * exceeds the device's per-workgroup LDS returns FDAS_EUNSUPPORTED (every
+ * K_max <= 2048 fits in 64 KB).
  */
 int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
                int64_t ld_power, void *hip_stream);

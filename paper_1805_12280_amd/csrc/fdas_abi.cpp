@@ -64,6 +64,7 @@ int perm_dispatch(int L, int tau, int e)
 struct fdas_plan {
     int device = 0;
     int num_cu = 0;
+    int lds_per_block = 0;     // LDS bytes one workgroup may use
     int32_t M = 0, k_max = 0, L = 0, D = 0, V = 0, kp = 0;
     int64_t input_len = 0;
     uint32_t flags = 0;
@@ -175,6 +176,8 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
     e = hipDeviceGetAttribute(&p->num_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&p->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
 
     const size_t bytes_H = sizeof(c32) * (size_t)M * L;
@@ -335,11 +338,16 @@ FDAS_API int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, floa
     a.M = plan->M;
     a.kp = plan->kp;
     a.tiles = (n + fdas::TD_TILE - 1) / fdas::TD_TILE;
-    // enough workgroups to cover the chip several times over
+    // template groups: small enough that their taps fit the LDS set aside
+    // for them, and numerous enough to cover the chip several times over
     const int64_t want_groups = std::max<int64_t>(1, (4LL * std::max(1, plan->num_cu) + a.tiles - 1) / a.tiles);
     const int64_t groups = std::min<int64_t>(plan->M, want_groups);
-    a.tg = (int)((plan->M + groups - 1) / groups);
+    a.tg = std::min((int)((plan->M + groups - 1) / groups), fdas::tdfir_group(a.kp, plan->M));
     a.groups = (plan->M + a.tg - 1) / a.tg;
+    const size_t lds = fdas::tdfir_lds_bytes(a.kp, a.tg);
+    if (lds > (size_t)plan->lds_per_block)
+        return fail(FDAS_EUNSUPPORTED, "fdas_tdfir: K_max=%d needs %zu bytes of LDS per workgroup (device: %d)",
+                    plan->k_max, lds, plan->lds_per_block);
     a.P = d_power;
     a.ld = ld_power;
     if (a.tiles > 0x7fffffffLL) return fail(FDAS_EINVAL, "n too large for one launch");

@@ -11,6 +11,7 @@ struct c32;
 constexpr int TD_THREADS = 256;              // work-items per TDFIR workgroup
 constexpr int TD_R = 8;                      // consecutive outputs per work-item
 constexpr int TD_TILE = TD_THREADS * TD_R;   // outputs per TDFIR workgroup
+constexpr int TD_TAP_BYTES = 4096;           // LDS for the taps of one TDFIR template group
 
 struct FusedArgs {
     const void *x;        // complex64 [n]
@@ -96,7 +97,8 @@ int fused_blocks_per_cu(int L);
 hipError_t launch_fused(const FusedArgs &a, hipStream_t st);
 hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int L, const c32 *twL,
                          hipStream_t st);
-size_t tdfir_lds_bytes(int kp);
+size_t tdfir_lds_bytes(int kp, int tg);
+int tdfir_group(int kp, int M);              // largest template group whose taps fit TD_TAP_BYTES
 int topk_blocks_per_cu(int L);
 hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
                             uint32_t *H16, hipStream_t st);

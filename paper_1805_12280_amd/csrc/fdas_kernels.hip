@@ -214,49 +214,67 @@ __global__ __launch_bounds__(L / 16) void segfft_kernel(const c32 *__restrict__ 
 // ---------------------------------------------------------------------------
 
 // Tile of TD_TILE outputs per workgroup, TD_R consecutive outputs per
-// work-item.  LDS holds x[i0 - kp .. i0 + TD_TILE) as two planes (real parts,
-// then imaginary parts) with one pad slot every 8 elements: work-items 8
-// elements apart then read 4-byte words 9 apart, so the 64 lanes of a read
-// touch 64 different banks.
+// work-item, for a group of tg templates (grid.y indexes the groups).  LDS
+// holds x[i0 - kp .. i0 + TD_TILE) as two planes (real parts, then
+// imaginary parts) with one pad slot every 8 elements: work-items 8 elements
+// apart then read 4-byte words 9 apart, so the 64 lanes of a read touch 64
+// different banks.  The taps of the group's templates follow the planes and
+// are read as broadcasts (every lane the same tap).  Taps and tile are
+// staged once, behind one barrier, so the template loop has no barrier; and
+// taps in LDS rather than in scalar registers keep every wait of the block
+// loop an in-order LDS wait (scalar loads complete out of order and share
+// the same counter, so each wait for a window read would drain them too).
 __device__ __forceinline__ int td_skew(int e) { return e + (e >> 3); }
+__host__ __device__ __forceinline__ int td_plane(int span) { return (span + (span >> 3) + 1 + 3) & ~3; }
+
+static_assert(TD_R == 8, "the window addressing assumes 8 outputs per work-item");
 
 __global__ __launch_bounds__(TD_THREADS) void tdfir_kernel(
     const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ taps,
     const int *__restrict__ tap_len, int M, int kp, int tg, float *__restrict__ P, int64_t ld)
 {
-    extern __shared__ float xsf[];
+    extern __shared__ __align__(16) float xsf[];
     const int tau = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * TD_TILE;
     const int64_t org = i0 - kp;
     const int span = TD_TILE + kp;
-    float *const xr = xsf, *const xi = xsf + td_skew(span) + 1;
+    const int plane = td_plane(span);         // a multiple of 4 floats: hs is 16-byte aligned
+    float *const xr = xsf, *const xi = xsf + plane;
+    c32 *const hs = reinterpret_cast<c32 *>(xsf + 2 * plane);
+    const int t_beg = blockIdx.y * tg, t_end = min(M, t_beg + tg);
     for (int l = tau; l < span; l += TD_THREADS) {
         const int64_t i = org + l;
         const c32 v = (i >= 0 && i < n) ? x[i] : mk(0.f, 0.f);
         xr[td_skew(l)] = v.re;
         xi[td_skew(l)] = v.im;
     }
+    const int ntaps = (t_end - t_beg) * kp;
+    for (int k = tau; k < ntaps; k += TD_THREADS) hs[k] = taps[(int64_t)t_beg * kp + k];
     __syncthreads();
-    const int t_end = min(M, (int)(blockIdx.y + 1) * tg);
-    for (int t = blockIdx.y * tg; t < t_end; ++t) {
-        const c32 *h = taps + (int64_t)t * kp;
+    // Window of work-item tau for the tap block starting at kb = 8 blk: tile
+    // elements l0 + c, c < 15, l0 = TD_R tau + kp - kb - 7 = 8 q + 1 with
+    // q = tau + kp / 8 - 1 - blk (kp is a multiple of 8), whose slots are
+    // 9 q + 1 + c + (c + 1) / 8: a per-work-item base, 9 words lower per
+    // block, plus compile-time offsets.
+    const int wb = 9 * (tau + kp / 8 - 1) + 1;
+    for (int t = t_beg; t < t_end; ++t) {
+        const c32 *const ht = hs + (t - t_beg) * kp;
         const int nblk = (tap_len[t] + 7) >> 3;
         c32 acc[TD_R];
 #pragma unroll
         for (int r = 0; r < TD_R; ++r) acc[r] = mk(0.f, 0.f);
         // one block of 8 taps: y[i] += sum_{k in block} x[i-k] h[k]
         for (int blk = 0; blk < nblk; ++blk) {
-            const int kb = blk * 8;
+            const float *const wr = xr + wb - 9 * blk, *const wi = xi + wb - 9 * blk;
             c32 win[15];
-            // window x[i - 7 .. i + 7] of this work-item's outputs: tile
-            // elements l0 + c with l0 = 8 q + 1 (kp and kb are multiples of
-            // 8), whose skewed slots are 9 q + 1 + c + (c + 1) / 8
-            const int l0 = TD_R * tau + kp - kb - 7;
 #pragma unroll
-            for (int c = 0; c < 15; ++c) win[c] = mk(xr[td_skew(l0 + c)], xi[td_skew(l0 + c)]);
+            for (int c = 0; c < 15; ++c) win[c] = mk(wr[c + (c + 1) / 8], wi[c + (c + 1) / 8]);
+            float4 h2[4];                   // the block's 8 taps, two per 16-byte read
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h2[e] = reinterpret_cast<const float4 *>(ht)[4 * blk + e];
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) {
-                const c32 hk = h[kb + kk];
+                const c32 hk = (kk & 1) ? mk(h2[kk >> 1].z, h2[kk >> 1].w) : mk(h2[kk >> 1].x, h2[kk >> 1].y);
 #pragma unroll
                 for (int r = 0; r < TD_R; ++r) {
                     const c32 xv = win[r - kk + 7];
@@ -355,17 +373,24 @@ hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int 
     return hipGetLastError();
 }
 
-size_t tdfir_lds_bytes(int kp)
+size_t tdfir_lds_bytes(int kp, int tg)
 {
-    // two planes of td_skew(span) + 1 floats
-    const int span = TD_TILE + kp;
-    return 2 * sizeof(float) * (size_t)(span + span / 8 + 1);
+    // two planes of td_skew(span) + 1 floats (rounded up to 16 bytes), then
+    // the taps of tg templates
+    return 2 * sizeof(float) * (size_t)td_plane(TD_TILE + kp) + sizeof(c32) * (size_t)kp * tg;
+}
+
+int tdfir_group(int kp, int M)
+{
+    // templates per workgroup: their taps within TD_TAP_BYTES of LDS
+    const int g = TD_TAP_BYTES / (int)(sizeof(c32) * kp);
+    return g < 1 ? 1 : (g > M ? M : g);
 }
 
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st)
 {
     dim3 grid((unsigned)a.tiles, (unsigned)a.groups), blk(TD_THREADS);
-    hipLaunchKernelGGL(tdfir_kernel, grid, blk, tdfir_lds_bytes(a.kp), st, (const c32 *)a.x, a.n,
+    hipLaunchKernelGGL(tdfir_kernel, grid, blk, tdfir_lds_bytes(a.kp, a.tg), st, (const c32 *)a.x, a.n,
                        (const c32 *)a.taps, a.tap_len, a.M, a.kp, a.tg, a.P, a.ld);
     return hipGetLastError();
 }
