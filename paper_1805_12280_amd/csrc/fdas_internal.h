@@ -13,6 +13,14 @@ constexpr int TD_R = 8;                      // consecutive outputs per work-ite
 constexpr int TD_TILE = TD_THREADS * TD_R;   // outputs per TDFIR workgroup
 constexpr int TD_TAP_BYTES = 4096;           // LDS for the taps of one TDFIR template group
 
+// Buffer resource word 3 of the gfx9 family (32-bit data format; offsets are
+// range-checked against num_records and out-of-range stores are dropped),
+// and the cache-policy bit of a streaming (non-temporal) store.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt at their maxima (gfx9 encoding)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 struct FusedArgs {
     const void *x;        // complex64 [n]
     int64_t n;

@@ -123,9 +123,16 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
             SG::fwd2(tau, X, bufC);
             __syncthreads();                    // bufC reads done before inv2 rewrites it
         }
-        // segment inside the input and the discard within row 0: rows 1..15
-        // are kept whole
-        const bool whole = D <= T && hi == L;
+        // Power stores go through a buffer resource spanning the segment's
+        // kept outputs P_t[sV, sV + hi - D): offsets are relative to segment
+        // point D, so a discarded point (j < D) has a negative offset, which
+        // wraps past the range, and a point past the input's end is past it
+        // too; the hardware drops both.  Every store is then unconditional,
+        // so the compiler counts all of them between the next template's
+        // spectrum loads and their use, and waits for those loads only (with
+        // predicated stores it could not, and each item waited for the
+        // previous item's stores to complete).
+        const int nkeep = hi - D;
         const int64_t u_end = min<int64_t>(u1, u + (M - t));     // this segment's items
         for (; u < u_end; ++u) {
             c32 v[16];
@@ -143,18 +150,12 @@ __global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
             SG::put_a_inv(tau, v, bufA);
             __syncthreads();
             SG::inv0(tau, v, bufA, tw0);
-            float *Pt = P + (int64_t)t * ld + base;     // uniform; written only at j >= D
-            if (whole) {
-                if (tau >= D) __builtin_nontemporal_store(norm2(v[0]), Pt + tau);
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(P + (int64_t)t * ld + s * V, 0, 4 * nkeep, kBufWord3);
 #pragma unroll
-                for (int m = 1; m < 16; ++m) __builtin_nontemporal_store(norm2(v[m]), Pt + tau + T * m);
-            } else {
-#pragma unroll
-                for (int m = 0; m < 16; ++m) {
-                    const int j = tau + T * m;
-                    if (j >= D && j < hi) __builtin_nontemporal_store(norm2(v[m]), Pt + j);
-                }
-            }
+            for (int m = 0; m < 16; ++m)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(norm2(v[m])), rs, 4 * (tau + T * m - D), 0,
+                                                      kNonTemporal);
             t = tn;
         }
     }

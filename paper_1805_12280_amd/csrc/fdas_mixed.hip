@@ -294,14 +294,6 @@ __global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restri
 // per (segment, template): Z = X H, inverse on the matrix cores
 // ---------------------------------------------------------------------------
 
-// Buffer resource word 3 of the gfx9 family (32-bit data format; offsets are
-// range-checked against num_records and out-of-range stores are dropped),
-// and the cache-policy bit of a streaming (non-temporal) store.
-constexpr int kBufWord3 = 0x00020000;
-constexpr int kNonTemporal = 2;
-// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt at their maxima (gfx9 encoding)
-constexpr int kWaitVmcnt0 = 0x0F70;
-
 // What one work-item holds for the inverse passes of every item: its lanes
 // of the 16-bit DFT matrices (pass A per column set r = 8 w + gam, with
 // W128^(p r) folded in; the DFT16 of passes B and C) and the pass-B output
