@@ -434,13 +434,15 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
     // Per-wave transpose of the powers: a wave's pass C yields outputs
-    // n = 64 w + j' + 128 m (j' < 64, m < 16) with 16 consecutive j' per lane
-    // group; staged as rows of 64 (pitch OT_ROW) they are stored back as 16
-    // rows of 64 consecutive floats.  The staging reuses the wave's own rows
-    // of bb (its pass-C operands, 16 x BJ words, dead once read), with
-    // output row m at row 4 g + 2 h + i (m = 8 h + 2 g + i), which puts the
-    // four lane groups 16 banks apart.
-    constexpr int OT_ROW = mix::BJ;
+    // n = 64 w + j' + 128 m (j' < 64, m < 16), lane (g, col) holding rows
+    // m = 8 h + 2 g + i of column j' = 16 gam + col.  Staged so that lane j'
+    // reads its 16 rows as four 16-byte chunks, they are stored back as 16
+    // rows of 64 consecutive floats.  Chunk c (rows 4c .. 4c + 3) of column
+    // j' sits at word 16 j' + 4 ((c + j' / 4) mod 4): the rotation by j' / 4
+    // makes both the 8-byte writes (rows m, m + 1 of a lane) and the 16-byte
+    // reads free of bank conflicts.  The staging reuses the wave's own rows
+    // of bb (its pass-C operands, 16 x BJ >= 1024 words, dead once read).
+    static_assert(16 * mix::BJ >= 1024, "power staging does not fit the wave's rows of bb");
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
     const MixBases xb(cc, bb, w, l);
@@ -510,20 +512,23 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const f4v d = ml.pass_c(h, bops[gam]);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)      // output n = j + 128 m, m = 8 h + 2 g + i, row 4 g + 2 h + i
-                    otw[(4 * g + 2 * h + i) * OT_ROW + 16 * gam + col] =
-                        (d[2 * i] * d[2 * i] + d[2 * i + 1] * d[2 * i + 1]) * pscale_u;
+                // rows m = 8 h + 2 g and m + 1 of column j' = 16 gam + col:
+                // chunk 2 h + g / 2, words 2 (g & 1) and 2 (g & 1) + 1
+                const int jc = 16 * gam + col;
+                *reinterpret_cast<float2 *>(otw + 16 * jc + 4 * ((2 * h + (g >> 1) + (jc >> 2)) & 3) + 2 * (g & 1)) =
+                    make_float2((d[0] * d[0] + d[1] * d[1]) * pscale_u, (d[2] * d[2] + d[3] * d[3]) * pscale_u);
             }
         }
         // 16 rows of 64 consecutive outputs per wave (the wave's own region:
         // its LDS accesses are executed in order, so its pass-C reads above
         // are done before these rows are overwritten; no barrier needed)
         const int off0 = 4 * (64 * w + l - D);
+        float4 pw[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pw[c] = *reinterpret_cast<const float4 *>(otw + 16 * l + 4 * ((c + (l >> 2)) & 3));
 #pragma unroll
         for (int m = 0; m < 16; ++m)
-            __builtin_amdgcn_raw_buffer_store_b32(
-                __float_as_uint(otw[(4 * ((m >> 1) & 3) + 2 * (m >> 3) + (m & 1)) * OT_ROW + l]), rs, off0 + 512 * m, 0,
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((&pw[m >> 2].x)[m & 3]), rs, off0 + 512 * m, 0,
                                                   kNonTemporal);
         next_a();
         xb.store_a(pa);
