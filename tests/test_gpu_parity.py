@@ -103,6 +103,27 @@ def test_ska_headline_full_plane(torch_cuda, fdas, L):
         assert any(abs(i - c.r0) < 300 and abs(w.bank.z[t] + c.z0) <= 1.5 for t, i, _ in top), c
 
 
+def test_ska_tdfir_full_plane(torch_cuda, fdas):
+    """The direct TDFIR on the 85 x 2^22 workload over the whole plane: at
+    this size its workgroups take the templates in groups of four (their taps
+    staged together in LDS) and the last group holds one template."""
+    w = datagen.ska_workload()
+    _say(f"[ska] {w.name} tdfir, full-plane oracle")
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=w.n, seg_fft=2048)
+    x = torch_cuda.from_numpy(w.x).cuda()
+    out = torch_cuda.empty((85, w.n), dtype=torch_cuda.float32, device="cuda")
+    plan.tdfir(x, out=out)
+    torch_cuda.cuda.synchronize()
+    st = PlaneStats()
+    for r0 in range(0, 85, 17):
+        rows = list(range(r0, r0 + 17))
+        st.add(rows, out[r0:r0 + 17].cpu().numpy(), oracle.power(w.x, w.bank.taps, w.bank.tap_len, rows=rows))
+    _say(st.summary())
+    assert st.norm_err <= FP32_TOL
+    ok, bad = st.topk_agree()
+    assert ok, bad
+
+
 @pytest.mark.parametrize("seed,n,m,k_max,L", [
     (1, 1, 3, 17, 1024),          # a single output
     (2, 924, 2, 101, 1024),       # n = V exactly
