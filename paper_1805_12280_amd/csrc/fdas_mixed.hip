@@ -435,13 +435,16 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
     // Per-wave transpose of the powers: a wave's pass C yields outputs
     // n = 64 w + j' + 128 m (j' < 64, m < 16), lane (g, col) holding rows
-    // m = 8 h + 2 g + i of column j' = 16 gam + col.  Staged so that lane j'
-    // reads its 16 rows as four 16-byte chunks, they are stored back as 16
-    // rows of 64 consecutive floats.  Chunk c (rows 4c .. 4c + 3) of column
-    // j' sits at word 16 j' + 4 ((c + j' / 4) mod 4): the rotation by j' / 4
-    // makes both the 8-byte writes (rows m, m + 1 of a lane) and the 16-byte
-    // reads free of bank conflicts.  The staging reuses the wave's own rows
-    // of bb (its pass-C operands, 16 x BJ >= 1024 words, dead once read).
+    // m = 8 h + 2 g + i of column j' = 16 gam + col.  Each lane writes its
+    // four rows of a column (2g, 2g + 1, 2g + 8, 2g + 9) as one 16-byte
+    // chunk; lane j' then reads its column's four chunks and stores the 16
+    // rows back as rows of 64 consecutive floats.  Chunk g of column j' sits
+    // at word 16 j' + 4 ((g + j' / 2) mod 4): any 8 consecutive lanes then
+    // touch 8 different 16-byte bank groups of 32 banks, on the writes and on
+    // the reads (16-byte accesses are served 8 lanes at a time: a rotation by
+    // j' / 4, distinct over 16 lanes of 64 banks, measured 16 more conflict
+    // cycles per wave and item).  The staging reuses the wave's own rows of
+    // bb (its pass-C operands, 16 x BJ >= 1024 words, dead once read).
     static_assert(16 * mix::BJ >= 1024, "power staging does not fit the wave's rows of bb");
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
@@ -509,27 +512,24 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
         for (int gam = 0; gam < 4; ++gam) {
             ml.pass_a(X, Hn, 2 * gam, pa[0][2 * gam], pa[1][2 * gam]);
             ml.pass_a(X, Hn, 2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const f4v d = ml.pass_c(h, bops[gam]);
-                // rows m = 8 h + 2 g and m + 1 of column j' = 16 gam + col:
-                // chunk 2 h + g / 2, words 2 (g & 1) and 2 (g & 1) + 1
-                const int jc = 16 * gam + col;
-                *reinterpret_cast<float2 *>(otw + 16 * jc + 4 * ((2 * h + (g >> 1) + (jc >> 2)) & 3) + 2 * (g & 1)) =
-                    make_float2((d[0] * d[0] + d[1] * d[1]) * pscale_u, (d[2] * d[2] + d[3] * d[3]) * pscale_u);
-            }
+            const f4v d0 = ml.pass_c(0, bops[gam]), d1 = ml.pass_c(1, bops[gam]);
+            const int jc = 16 * gam + col;
+            *reinterpret_cast<float4 *>(otw + 16 * jc + 4 * ((g + (jc >> 1)) & 3)) =
+                make_float4((d0[0] * d0[0] + d0[1] * d0[1]) * pscale_u, (d0[2] * d0[2] + d0[3] * d0[3]) * pscale_u,
+                            (d1[0] * d1[0] + d1[1] * d1[1]) * pscale_u, (d1[2] * d1[2] + d1[3] * d1[3]) * pscale_u);
         }
         // 16 rows of 64 consecutive outputs per wave (the wave's own region:
         // its LDS accesses are executed in order, so its pass-C reads above
         // are done before these rows are overwritten; no barrier needed)
         const int off0 = 4 * (64 * w + l - D);
-        float4 pw[4];
+        float4 pw[4];                  // pw[gq] = rows 2gq, 2gq + 1, 2gq + 8, 2gq + 9
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pw[c] = *reinterpret_cast<const float4 *>(otw + 16 * l + 4 * ((c + (l >> 2)) & 3));
+        for (int gq = 0; gq < 4; ++gq)
+            pw[gq] = *reinterpret_cast<const float4 *>(otw + 16 * l + 4 * ((gq + (l >> 1)) & 3));
 #pragma unroll
         for (int m = 0; m < 16; ++m)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((&pw[m >> 2].x)[m & 3]), rs, off0 + 512 * m, 0,
-                                                  kNonTemporal);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((&pw[(m >> 1) & 3].x)[2 * (m >> 3) + (m & 1)]), rs,
+                                                  off0 + 512 * m, 0, kNonTemporal);
         next_a();
         xb.store_a(pa);
         __syncthreads();
