@@ -439,13 +439,13 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     // four rows of a column (2g, 2g + 1, 2g + 8, 2g + 9) as one 16-byte
     // chunk; lane j' then reads its column's four chunks and stores the 16
     // rows back as rows of 64 consecutive floats.  Chunk g of column j' sits
-    // at word 16 j' + 4 ((g + j' / 2) mod 4): any 8 consecutive lanes then
-    // touch 8 different 16-byte bank groups of 32 banks, on the writes and on
-    // the reads (16-byte accesses are served 8 lanes at a time: a rotation by
-    // j' / 4, distinct over 16 lanes of 64 banks, measured 16 more conflict
-    // cycles per wave and item).  The staging reuses the wave's own rows of
-    // bb (its pass-C operands, 16 x BJ >= 1024 words, dead once read).
-    static_assert(16 * mix::BJ >= 1024, "power staging does not fit the wave's rows of bb");
+    // at mix::stage_word(j', g), rotated so that the 16-byte writes and
+    // reads are free of bank conflicts (16-byte accesses are served 8 lanes
+    // at a time: a rotation by j' / 4, distinct over 16 lanes of 64 banks
+    // only, measured 16 more conflict cycles per wave and item).  The
+    // staging reuses the wave's own rows of bb (its pass-C operands,
+    // 16 x BJ >= 1024 words, dead once read).
+    static_assert(16 * mix::BJ >= mix::STAGE_WORDS, "power staging does not fit the wave's rows of bb");
 
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
     const MixBases xb(cc, bb, w, l);
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
             ml.pass_a(X, Hn, 2 * gam + 1, pa[0][2 * gam + 1], pa[1][2 * gam + 1]);
             const f4v d0 = ml.pass_c(0, bops[gam]), d1 = ml.pass_c(1, bops[gam]);
             const int jc = 16 * gam + col;
-            *reinterpret_cast<float4 *>(otw + 16 * jc + 4 * ((g + (jc >> 1)) & 3)) =
+            *reinterpret_cast<float4 *>(otw + mix::stage_word(jc, g)) =
                 make_float4((d0[0] * d0[0] + d0[1] * d0[1]) * pscale_u, (d0[2] * d0[2] + d0[3] * d0[3]) * pscale_u,
                             (d1[0] * d1[0] + d1[1] * d1[1]) * pscale_u, (d1[2] * d1[2] + d1[3] * d1[3]) * pscale_u);
         }
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
         float4 pw[4];                  // pw[gq] = rows 2gq, 2gq + 1, 2gq + 8, 2gq + 9
 #pragma unroll
         for (int gq = 0; gq < 4; ++gq)
-            pw[gq] = *reinterpret_cast<const float4 *>(otw + 16 * l + 4 * ((gq + (l >> 1)) & 3));
+            pw[gq] = *reinterpret_cast<const float4 *>(otw + mix::stage_word(l, gq));
 #pragma unroll
         for (int m = 0; m < 16; ++m)
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint((&pw[(m >> 1) & 3].x)[2 * (m >> 3) + (m & 1)]), rs,

@@ -40,8 +40,10 @@ constexpr int L = 2048;
 constexpr int T = 128;          // work-items per transform
 
 // LDS exchanges, in 32-bit words (one complex 16-bit value each).  Both are
-// laid out so that every access of the passes below touches 64 distinct
-// banks per 64 lanes (16-byte accesses: distinct 4-bank groups per 16 lanes).
+// laid out so that every access of the passes below touches distinct banks:
+// 4-byte accesses 64 banks per 64 lanes; 16-byte accesses distinct 4-bank
+// groups per 16 lanes of 64 banks and per 8 lanes of 32 banks (counters show
+// 16-byte accesses served 8 lanes at a time).
 //   c[p][k1][r]  at k1 * CK + 16 p + r            (pass A writes, B reads)
 //   b[k1][j]     at (j / 4) * BJ + 4 k1 + j % 4   (pass B writes, C reads)
 constexpr int CK = 132;         // 128 + 4: consecutive k1 rows move 4 banks
@@ -50,6 +52,16 @@ constexpr int CC_WORDS = 16 * CK;
 constexpr int BB_WORDS = 32 * BJ;
 FDAS_HD int cc_word(int p, int k1, int r) { return k1 * CK + 16 * p + r; }
 FDAS_HD int bb_word(int j, int k1) { return (j >> 2) * BJ + 4 * k1 + (j & 3); }
+
+// Power staging of one wave (float words, 16 per output column j' < 64):
+// chunk g (rows 2g, 2g + 1, 2g + 8, 2g + 9 of the column, one 16-byte write
+// by lane (g, col) of pass C) at 16 j' + 4 ((g + j'/2 + j'/8) mod 4); lane j'
+// reads its column's four chunks.  The rotation j'/2 + j'/8 takes all four
+// values over the lanes of one parity in any 8 consecutive lanes and over
+// the lanes of one residue mod 4 in any 16, so the writes and reads are
+// conflict-free under both bank models above.
+constexpr int STAGE_WORDS = 64 * 16;
+FDAS_HD int stage_word(int jcol, int g) { return 16 * jcol + 4 * ((g + (jcol >> 1) + (jcol >> 3)) & 3); }
 
 // Pass A: group gam of wave w is r = 8 w + gam with columns k1 = col; lane
 // (col, g) takes s = 2 g + i (value v = 2 gam + i) and returns p = 2 g, 2 g + 1.

@@ -187,19 +187,23 @@ int main()
     }
     CHECK(err <= 1e-9 * mx, "passes differ from the inverse DFT: %g (max %g)", err, mx);
 
-    // ---- LDS bank conflicts of the kernel's accesses (64 banks x 4 bytes) ----
-    // An access of W words per lane is served W * 64 / 64 lanes at a time in
-    // groups of 64 / W lanes; it is conflict-free when each group covers
-    // distinct banks.
-    auto conflict_free = [](const int *addr, int W) {
-        const int G = 64 / W;
+    // ---- LDS bank conflicts of the kernel's accesses ----
+    // An access of W words per lane over B banks of 4 bytes is served B / W
+    // lanes at a time; it is conflict-free when each group of lanes covers
+    // distinct banks.  Every access is checked with 64 banks; the 16-byte
+    // ones also with 32 (16-byte accesses measure as 8 lanes at a time).
+    auto conflict_free_b = [](const int *addr, int W, int B) {
+        const int G = B / W;
         for (int g0 = 0; g0 < 64; g0 += G) {
             std::set<int> banks;
             for (int l = g0; l < g0 + G; ++l)
-                for (int k = 0; k < W; ++k) banks.insert((addr[l] + k) & 63);
+                for (int k = 0; k < W; ++k) banks.insert((addr[l] + k) % B);
             if ((int)banks.size() != G * W) return false;
         }
         return true;
+    };
+    auto conflict_free = [&](const int *addr, int W) {
+        return conflict_free_b(addr, W, 64) && (W != 4 || conflict_free_b(addr, W, 32));
     };
     int addr[64];
     for (int w = 0; w < 2; ++w) {
@@ -222,6 +226,26 @@ int main()
                 for (int l = 0; l < 64; ++l) addr[l] = bb_word(16 * (4 * w + gam) + (l & 15), 4 * (l >> 4) + e);
                 CHECK(conflict_free(addr, 1), "pass C load w=%d gam=%d e=%d", w, gam, e);
             }
+    }
+    // ---- power staging (16 floats per column, chunks of 4) ----
+    {
+        std::set<int> words;
+        for (int j = 0; j < 64; ++j)
+            for (int g = 0; g < 4; ++g) {
+                const int a = stage_word(j, g);
+                CHECK(a >= 0 && a + 4 <= STAGE_WORDS && a % 4 == 0, "stage_word out of range or misaligned");
+                for (int k = 0; k < 4; ++k) words.insert(a + k);
+            }
+        CHECK((int)words.size() == STAGE_WORDS, "stage_word is not a bijection");
+        CHECK(16 * BJ >= STAGE_WORDS, "staging does not fit a wave's rows of bb");
+        for (int gam = 0; gam < 4; ++gam) {    // writes: lane (g, col) -> column 16 gam + col, chunk g
+            for (int l = 0; l < 64; ++l) addr[l] = stage_word(16 * gam + (l & 15), l >> 4);
+            CHECK(conflict_free(addr, 4), "staging write gam=%d", gam);
+        }
+        for (int g = 0; g < 4; ++g) {          // reads: lane j' -> its column, chunk g
+            for (int l = 0; l < 64; ++l) addr[l] = stage_word(l, g);
+            CHECK(conflict_free(addr, 4), "staging read g=%d", g);
+        }
     }
     if (failures) return 1;
     std::printf("ok max|err| %.3g of %.3g\n", err, mx);
