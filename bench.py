@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "template-samples/s (85 tpl x 2^22 pts) + HBM roofline frac; served p50/p99 ms"
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector: 256 CU x 64 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
-KERNEL_SOURCES = ("paper_1805_12280_amd/csrc/seg_fft.h", "paper_1805_12280_amd/csrc/fdas_kernels.hip")
+KERNEL_SOURCES = ("paper_1805_12280_amd/csrc/seg_fft.h", "paper_1805_12280_amd/csrc/fdas_internal.h",
+                  "paper_1805_12280_amd/csrc/fdas_kernels.hip")
 TRAFFIC_FILES = {L: os.path.join(ROOT, "profiles", f"fdfir_fused_ska-85x2^22_L{L}_traffic.md")
                  for L in (1024, 2048, 4096)}
 

@@ -1,0 +1,59 @@
+"""Host logic of bench.py: the algorithmic byte and operation counts behind
+the roofline figures, the per-step percentiles, the lookup of measured HBM
+traffic in the committed profile summaries, and the refusal of more than
+one GPU.  No GPU is used."""
+import math
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+N, M, K_MAX = 1 << 22, 85, 101
+
+
+def test_algorithmic_bytes_headline():
+    # the input read once (8 N), the float32 plane written once (4 M N) and
+    # the template spectra read once (8 M L): 1461.0 MB at L = 2048
+    assert bench.algorithmic_bytes(N, M, 2048) == 8 * N + 4 * M * N + 8 * M * 2048
+    assert abs(bench.algorithmic_bytes(N, M, 2048) / 1e6 - 1461.0) < 0.05
+
+
+@pytest.mark.parametrize("L,expect", [(1024, 2.343e10), (2048, 2.419e10), (4096, 2.546e10), (8192, 2.701e10)])
+def test_nominal_operations(L, expect):
+    # 5 L log2 L per transform (one forward per segment, one inverse per
+    # segment and template), 6 per complex product, 3 per power, with the
+    # minimal overlap V = L - (K_max - 1)
+    got = bench.nominal_flops(N, M, L, K_MAX)
+    assert abs(got / expect - 1) < 1e-3, (L, got)
+    v = L - (K_MAX - 1)
+    s = math.ceil(N / v)
+    assert got == s * (M * (5 * L * math.log2(L) + 6 * L + 3 * v) + 5 * L * math.log2(L))
+
+
+def test_percentiles_pick_order_statistics():
+    xs = [float(v) for v in range(100, 0, -1)]      # 100 .. 1, unsorted input
+    p = bench.percentiles(xs)
+    assert p == {"p10": 11.0, "median": 51.0, "p90": 90.0}
+    assert bench.percentiles([3.0]) == {"p10": 3.0, "median": 3.0, "p90": 3.0}
+
+
+def test_measured_traffic_tracks_kernel_source(monkeypatch):
+    # the committed L = 2048 summary was taken on the current kernel source
+    t = bench.measured_traffic(2048)
+    assert t is not None and 1.4e9 < t < 1.6e9
+    # a different source hash makes the figure unusable (reported as null)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic(2048) is None
+    assert bench.measured_traffic(8192) is None        # no summary for this length
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
