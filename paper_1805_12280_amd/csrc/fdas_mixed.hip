@@ -216,9 +216,13 @@ __device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16,
     using SG = Seg<2048>;
     using HF = Half<BF>;
     constexpr int L = mix::L, T = mix::T;
-    __shared__ c32 lds[2 * SG::LDS_ELEMS];
+    // One LDS buffer serves both exchanges and the redistribution (2176
+    // slots of 17 per 16 frequencies), one barrier more than two buffers but
+    // half the LDS, so twice the workgroups fit a CU.
+    constexpr int LDS_SLOTS = SG::LDS_ELEMS > L + L / 16 ? SG::LDS_ELEMS : L + L / 16;
+    __shared__ c32 lds[LDS_SLOTS];
     __shared__ float s_max[2];
-    c32 *bufA = lds, *bufC = lds + SG::LDS_ELEMS;
+    c32 *const bufA = lds, *const bufC = lds;
     const int tau = threadIdx.x, w = tau >> 6, l = tau & 63, col = l & 15, g = l >> 4;
 
     c32 v[16];
@@ -239,6 +243,7 @@ __device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16,
         __syncthreads();
         SG::fwd1(tau, v, bufA, tw1);
     }
+    __syncthreads();                       // pass-1 reads done before bufC (the same buffer) is written
     SG::put_c(tau, v, bufC);
     __syncthreads();
     SG::fwd2(tau, v, bufC);
