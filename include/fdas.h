@@ -91,7 +91,9 @@ typedef struct {
  *   M          templates, >= 1.
  *   K_max      taps per row of `taps`, >= 1 and <= seg_fft / 2.
  *   input_len  largest input length the plan will be given, >= 1.
- *   seg_fft    L in {1024, 2048, 4096}, or 0 for the default 2048.
+ *   seg_fft    L in {1024, 2048, 4096, 8192}, or 0 for the default 2048.
+ *              L = 8192 (K_max up to 4096) needs 128 KB of LDS per
+ *              workgroup; a device that has less returns FDAS_EUNSUPPORTED.
  *   flags      FDAS_FP32, FDAS_FP16 or FDAS_BF16, optionally |
  *              FDAS_TAPS_ON_DEVICE; anything else returns FDAS_EUNSUPPORTED.
  *              FDAS_FP16/FDAS_BF16 ("mixed" plans): the input spectrum and the
@@ -172,7 +174,7 @@ int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, float *d_p
  * input tile and the taps of a few templates in LDS, about
  * 9 * (2048 + K_max) + max(4096, 8 * K_max) bytes; a K_max for which that
  * exceeds the device's per-workgroup LDS returns FDAS_EUNSUPPORTED (every
- * K_max <= 2048 fits in 64 KB).
+ * K_max <= 2048 fits in 64 KB; K_max = 4096 needs 88 KB).
  */
 int fdas_tdfir(const fdas_plan *plan, const void *d_in, int64_t n, float *d_power,
                int64_t ld_power, void *hip_stream);

@@ -5,7 +5,7 @@ The segment transform length L trades the overlap discarded per segment
 paper finds the best N_FT experimentally per device (Section 3.3, Fig. 7/8).
 The persistent grid's size (workgroups per CU) trades latency hiding against
 how many templates share each forward transform.  Here every admissible L in
-{1024, 2048, 4096} (K_max <= L/2), each with the full and the half grid, is
+{1024, 2048, 4096, 8192} (K_max <= L/2), each with the full and the half grid, is
 timed on the device with the call shape that will be used (plane or batched
 top-K), and the fastest pair is kept.  Results are cached in a JSON file
 keyed by the device name, bank shape and length profile, so a server or
@@ -19,7 +19,7 @@ import time
 
 from . import fdas
 
-CANDIDATES = (1024, 2048, 4096)
+CANDIDATES = (1024, 2048, 4096, 8192)
 
 
 def cache_path() -> str:

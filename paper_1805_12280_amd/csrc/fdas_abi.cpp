@@ -46,7 +46,7 @@ constexpr int kVariantFusedPersistent = 1;
 constexpr int kVariantMixedFp16 = 2;
 constexpr int kVariantMixedBf16 = 3;
 
-bool supported_l(int L) { return L == 1024 || L == 2048 || L == 4096; }
+bool supported_l(int L) { return L == 1024 || L == 2048 || L == 4096 || L == 8192; }
 
 template <int L> int perm_of(int tau, int e) { return fdas::Seg<L>::perm(tau, e); }
 
@@ -55,7 +55,8 @@ int perm_dispatch(int L, int tau, int e)
     switch (L) {
     case 1024: return perm_of<1024>(tau, e);
     case 2048: return perm_of<2048>(tau, e);
-    default: return perm_of<4096>(tau, e);
+    case 4096: return perm_of<4096>(tau, e);
+    default: return perm_of<8192>(tau, e);
     }
 }
 
@@ -140,7 +141,7 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     if (K_max < 1) return fail(FDAS_EINVAL, "K_max=%d < 1", K_max);
     if (input_len < 1) return fail(FDAS_EINVAL, "input_len=%lld < 1", (long long)input_len);
     const int L = seg_fft == 0 ? 2048 : seg_fft;
-    if (!supported_l(L)) return fail(FDAS_EINVAL, "seg_fft=%d not in {1024, 2048, 4096}", seg_fft);
+    if (!supported_l(L)) return fail(FDAS_EINVAL, "seg_fft=%d not in {1024, 2048, 4096, 8192}", seg_fft);
     if (K_max > L / 2) return fail(FDAS_EINVAL, "K_max=%d > seg_fft/2=%d", K_max, L / 2);
     const bool on_dev = (flags & FDAS_TAPS_ON_DEVICE) != 0;
     hipStream_t st = (hipStream_t)hip_stream;
@@ -179,6 +180,12 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&p->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+    // the transform's two exchange buffers (L = 8192: 128 KB) must fit a workgroup's LDS
+    if (fdas::fused_lds_bytes(L) > (size_t)p->lds_per_block) {
+        free_plan(p);
+        return fail(FDAS_EUNSUPPORTED, "seg_fft=%d needs %zu bytes of LDS per workgroup (device: %d)", L,
+                    fdas::fused_lds_bytes(L), p->lds_per_block);
+    }
 
     const size_t bytes_H = sizeof(c32) * (size_t)M * L;
     const size_t bytes_tw = sizeof(c32) * (size_t)L;

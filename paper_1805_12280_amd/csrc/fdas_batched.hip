@@ -24,7 +24,7 @@ namespace fdas {
 // it touches: stage[(b * max_slots + slot) * K + r], hdr[b * max_slots + slot]
 // = (array, entries), nslots[b] = lists written.
 template <int L>
-__global__ __launch_bounds__(L / 16, 2) void fdfir_topk_kernel(
+__global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_topk_kernel(
     BatchSet bs, const c32 *__restrict__ H, const c32 *__restrict__ twL, int M, int D, int V, int K,
     int64_t items, Cand *__restrict__ stage, int2 *__restrict__ hdr, int *__restrict__ nslots,
     int max_slots)
@@ -316,6 +316,7 @@ int topk_blocks_per_cu(int L)
     case 1024: return topk_blocks_per_cu_of<1024>();
     case 2048: return topk_blocks_per_cu_of<2048>();
     case 4096: return topk_blocks_per_cu_of<4096>();
+    case 8192: return topk_blocks_per_cu_of<8192>();
     default: return 1;
     }
 }
@@ -333,6 +334,7 @@ hipError_t launch_topk(const TopkArgs &a, hipStream_t st)
     case 1024: launch_topk_t<1024>(a, st); break;
     case 2048: launch_topk_t<2048>(a, st); break;
     case 4096: launch_topk_t<4096>(a, st); break;
+    case 8192: launch_topk_t<8192>(a, st); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

@@ -106,6 +106,7 @@ hipError_t launch_fused(const FusedArgs &a, hipStream_t st);
 hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int L, const c32 *twL,
                          hipStream_t st);
 size_t tdfir_lds_bytes(int kp, int tg);
+size_t fused_lds_bytes(int L);              // LDS of the float32 template-loop kernels at segment length L
 int tdfir_group(int kp, int M);              // largest template group whose taps fit TD_TAP_BYTES
 int topk_blocks_per_cu(int L);
 hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,

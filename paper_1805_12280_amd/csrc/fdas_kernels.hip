@@ -77,7 +77,7 @@ __global__ void tspec_kernel(const c32 *__restrict__ taps, const int *__restrict
 // items and the forward transform under a branch, X is a loop-carried value
 // and the compiler copies its 32 registers twice per item.
 template <int L>
-__global__ __launch_bounds__(L / 16, 2) void fdfir_fused_kernel(
+__global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_fused_kernel(
     const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ H, const c32 *__restrict__ twL,
     int M, int D, int V, int64_t items, float *__restrict__ P, int64_t ld)
 {
@@ -313,6 +313,7 @@ hipError_t launch_tspec(const c32 *taps, const int *tap_len, int kp, int M, int 
     case 1024: hipLaunchKernelGGL(tspec_kernel<1024>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
     case 2048: hipLaunchKernelGGL(tspec_kernel<2048>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
     case 4096: hipLaunchKernelGGL(tspec_kernel<4096>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
+    case 8192: hipLaunchKernelGGL(tspec_kernel<8192>, grid, blk, 0, st, taps, tap_len, kp, M, H); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -331,6 +332,7 @@ int fused_blocks_per_cu(int L)
     case 1024: return blocks_per_cu_of<1024>();
     case 2048: return blocks_per_cu_of<2048>();
     case 4096: return blocks_per_cu_of<4096>();
+    case 8192: return blocks_per_cu_of<8192>();
     default: return 1;
     }
 }
@@ -348,6 +350,7 @@ hipError_t launch_fused(const FusedArgs &a, hipStream_t st)
     case 1024: launch_fused_t<1024>(a, st); break;
     case 2048: launch_fused_t<2048>(a, st); break;
     case 4096: launch_fused_t<4096>(a, st); break;
+    case 8192: launch_fused_t<8192>(a, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -368,6 +371,7 @@ hipError_t launch_segfft(const void *in, void *out, int64_t count, int dir, int 
         FDAS_SEGFFT_CASE(1024)
         FDAS_SEGFFT_CASE(2048)
         FDAS_SEGFFT_CASE(4096)
+        FDAS_SEGFFT_CASE(8192)
     default: return hipErrorInvalidValue;
     }
 #undef FDAS_SEGFFT_CASE
@@ -379,6 +383,13 @@ size_t tdfir_lds_bytes(int kp, int tg)
     // two planes of td_skew(span) + 1 floats (rounded up to 16 bytes), then
     // the taps of tg templates
     return 2 * sizeof(float) * (size_t)td_plane(TD_TILE + kp) + sizeof(c32) * (size_t)kp * tg;
+}
+
+size_t fused_lds_bytes(int L)
+{
+    // two exchange buffers of 16 rows of L / 16 + 1 complex values (the
+    // batched kernel adds its candidate lists, 1 KB)
+    return 2 * sizeof(c32) * 16 * (size_t)(L / 16 + 1) + 1024;
 }
 
 int tdfir_group(int kp, int M)

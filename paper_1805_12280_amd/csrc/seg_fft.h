@@ -5,7 +5,8 @@
 // This is the FFT/IFFT engine role of Section 4.2 (one engine used for the
 // forward round and the inverse round, as in AOLS-FD), recast for a GPU:
 // a three-pass mixed-radix Cooley-Tukey transform, L = 16 * 16 * R2 with
-// R2 = L / 256 in {4, 8, 16}.
+// R2 = L / 256 in {4, 8, 16}; at L = 8192 the last pass (R2 = 32) is itself
+// split, 32 = 16 x 2, with one more exchange (see Seg<8192> below).
 //
 // Forward (decimation in frequency), natural-order input, work-item tau:
 //   pass 0  j = tau:            a[j][k1] = DFT16_m(w[j + T m]) * W_L^(j k1)
@@ -69,6 +70,19 @@ template <int S, int E> FDAS_HD c32 w16()
                                0.70710678118654752440, 0.92387953251128673848};
     // sin(2 pi E / 16) = cos(2 pi (E - 4) / 16)
     return mk((float)kC[E & 15], (float)(S * kC[(E + 12) & 15]));
+}
+
+// exp(S * 2 pi i * E / 32) (E in 0..15)
+template <int S> FDAS_HD c32 w32(int E)
+{
+    constexpr double kC[16] = {1.0, 0.98078528040323044913, 0.92387953251128673848, 0.83146961230254523708,
+                               0.70710678118654752440, 0.55557023301960222474, 0.38268343236508978178,
+                               0.19509032201612826785, 0.0, -0.19509032201612826785, -0.38268343236508978178,
+                               -0.55557023301960222474, -0.70710678118654752440, -0.83146961230254523708,
+                               -0.92387953251128673848, -0.98078528040323044913};
+    // sin(2 pi E / 32) = cos(2 pi (8 - E) / 32), E <= 8; = cos(2 pi (E - 8) / 32) mirrored above
+    const double sn = E <= 8 ? kC[8 - E] : kC[E - 8];
+    return mk((float)kC[E], (float)(S * sn));
 }
 
 // a * exp(S 2 pi i E / 16), with the trivial angles done without multiplies.
@@ -273,11 +287,11 @@ template <int R, int S> FDAS_HD void dft_prod(const c32 *a, const c32 *b, c32 *v
 template <int L> struct Seg {
     static constexpr int T = L / 16;       // work-items per transform
     static constexpr int R2 = L / 256;     // radix of the last forward pass
-    static constexpr int G = 16 / R2;      // last-pass butterflies per work-item
+    static constexpr int G = R2 <= 16 ? 16 / R2 : 1;   // last-pass butterflies per work-item (R2 <= 16)
     static constexpr int PAD = 1;          // LDS row padding (complex elements)
     static constexpr int ROW = T + PAD;
     static constexpr int LDS_ELEMS = 16 * ROW;
-    static_assert(L == 1024 || L == 2048 || L == 4096, "segment length");
+    static_assert(L == 1024 || L == 2048 || L == 4096 || L == 8192, "segment length");
 
     // LDS slots of the two exchanges (one buffer, used one after the other)
     FDAS_HD static int a_slot(int k1, int j) { return k1 * ROW + j; }
@@ -289,8 +303,14 @@ template <int L> struct Seg {
     // Frequency held by work-item tau in register e after the forward passes.
     FDAS_HD static int perm(int tau, int e)
     {
-        int g = e / R2, s = e % R2;
-        return k1_of(tau) + 16 * (p_of(tau) * G + g) + 256 * s;
+        if constexpr (L == 8192) {
+            // pass 2b work-item (k1, r, h) = (tau % 16, tau / 16 % 16, tau / 256):
+            // register e = s0' + 8 s1 holds s' = 8 h + s0' + 16 s1
+            return k1_of(tau) + 16 * ((tau >> 4) & 15) + 256 * (8 * (tau >> 8) + (e & 7) + 16 * (e >> 3));
+        } else {
+            int g = e / R2, s = e % R2;
+            return k1_of(tau) + 16 * (p_of(tau) * G + g) + 256 * s;
+        }
     }
 
     // Per-work-item twiddles, held in registers for the life of a workgroup:
@@ -335,34 +355,123 @@ template <int L> struct Seg {
 #pragma unroll
         for (int r = 0; r < 16; ++r) lds[c_slot(k1, r, p)] = v[r];
     }
-    // v[e] = X[perm(tau, e)] on exit.
-    FDAS_HD static void fwd2(int tau, c32 *v, const c32 *lds)
+    // v[e] = X[perm(tau, e)] on exit.  At L = 8192 the pass is split and
+    // reuses lds for its own exchange, behind two barriers of its own.
+    FDAS_HD static void fwd2(int tau, c32 *v, c32 *lds)
     {
-        const int k1 = k1_of(tau), p = p_of(tau);
+        if constexpr (L == 8192) {
+            c32 d[16];
+            fwd2a(tau, d, lds);
+            __syncthreads();
+            put_e(tau, d, lds);
+            __syncthreads();
+            fwd2b(tau, v, lds);
+        } else {
+            const int k1 = k1_of(tau), p = p_of(tau);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            c32 d[R2];
+            for (int g = 0; g < G; ++g) {
+                c32 d[R2];
 #pragma unroll
-            for (int pp = 0; pp < R2; ++pp) d[pp] = lds[c_slot(k1, p * G + g, pp)];
-            dft<R2, -1>(d);
+                for (int pp = 0; pp < R2; ++pp) d[pp] = lds[c_slot(k1, p * G + g, pp)];
+                dft<R2, -1>(d);
 #pragma unroll
-            for (int s = 0; s < R2; ++s) v[g * R2 + s] = d[s];
+                for (int s = 0; s < R2; ++s) v[g * R2 + s] = d[s];
+            }
         }
     }
 
     // -- inverse --
     // Z[perm(tau, e)] = X[e] * Hs[e] (the pointwise product, taken inside the
-    // first butterfly layer); writes c' to LDS.
+    // first butterfly layer); writes c' to LDS.  At L = 8192 the pass is
+    // split and reuses lds for its own exchange (two barriers of its own).
     FDAS_HD static void inv2(int tau, const c32 *X, const c32 *Hs, c32 *lds)
     {
-        const int k1 = k1_of(tau), p = p_of(tau);
+        if constexpr (L == 8192) {
+            inv2b(tau, X, Hs, lds);
+            __syncthreads();
+            c32 d[16];
+            inv2a(tau, d, lds);
+            __syncthreads();
+            put_c_inv(tau, d, lds);
+        } else {
+            const int k1 = k1_of(tau), p = p_of(tau);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            c32 d[R2];
-            dft_prod<R2, +1>(X + g * R2, Hs + g * R2, d);
+            for (int g = 0; g < G; ++g) {
+                c32 d[R2];
+                dft_prod<R2, +1>(X + g * R2, Hs + g * R2, d);
 #pragma unroll
-            for (int pp = 0; pp < R2; ++pp) lds[c_slot(k1, p * G + g, pp)] = d[pp];
+                for (int pp = 0; pp < R2; ++pp) lds[c_slot(k1, p * G + g, pp)] = d[pp];
+            }
         }
+    }
+
+    // -- the split last pass at L = 8192 (32 = 16 x 2) --
+    // With p = p0 + 2 p1 and s' = s0 + 16 s1 (p0, s1 < 2; p1, s0 < 16),
+    //   X[k1 + 16 r + 256 s'] = sum_p0 W2^(p0 s1) W32^(p0 s0) sum_p1 W16^(p1 s0) c[k1][p][r].
+    // Pass 2a, work-item (k1, r, p0) = (tau % 16, tau / 16 % 16, tau / 256):
+    //   e[k1][p0][r][s0] = W32^(p0 s0) DFT16_p1(c[k1][p0 + 2 p1][r]);
+    // pass 2b, work-item (k1, r, h): radix 2 over p0 for s0 = 8 h .. 8 h + 7.
+    // p0 and h are uniform over a wavefront.  The inverse runs the transpose
+    // (2b' with the product, then 2a' with conjugate twiddles).
+    FDAS_HD static int e_slot(int k1, int r, int p0, int s0) { return k1 * ROW + 32 * r + 2 * s0 + p0; }
+    FDAS_HD static void fwd2a(int tau, c32 *d, const c32 *lds)
+    {
+        const int k1 = k1_of(tau), r = (tau >> 4) & 15, p0 = tau >> 8;
+#pragma unroll
+        for (int p1 = 0; p1 < 16; ++p1) d[p1] = lds[c_slot(k1, r, p0 + 2 * p1)];
+        dft16<-1>(d);
+        if (p0) {
+#pragma unroll
+            for (int s0 = 1; s0 < 16; ++s0) d[s0] = mul(d[s0], w32<-1>(s0));
+        }
+    }
+    FDAS_HD static void put_e(int tau, const c32 *d, c32 *lds)
+    {
+        const int k1 = k1_of(tau), r = (tau >> 4) & 15, p0 = tau >> 8;
+#pragma unroll
+        for (int s0 = 0; s0 < 16; ++s0) lds[e_slot(k1, r, p0, s0)] = d[s0];
+    }
+    FDAS_HD static void fwd2b(int tau, c32 *v, const c32 *lds)
+    {
+        const int k1 = k1_of(tau), r = (tau >> 4) & 15, h = tau >> 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const c32 a = lds[e_slot(k1, r, 0, 8 * h + i)], b = lds[e_slot(k1, r, 1, 8 * h + i)];
+            v[i] = add(a, b);
+            v[i + 8] = sub(a, b);
+        }
+    }
+    FDAS_HD static void inv2b(int tau, const c32 *X, const c32 *Hs, c32 *lds)
+    {
+        const int k1 = k1_of(tau), r = (tau >> 4) & 15, h = tau >> 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const c32 a[2] = {X[i], X[i + 8]}, b[2] = {Hs[i], Hs[i + 8]};
+            c32 d[2];
+            dft_prod<2, +1>(a, b, d);
+            lds[e_slot(k1, r, 0, 8 * h + i)] = d[0];
+            lds[e_slot(k1, r, 1, 8 * h + i)] = d[1];
+        }
+    }
+    FDAS_HD static void inv2a(int tau, c32 *d, const c32 *lds)
+    {
+        const int k1 = k1_of(tau), r = (tau >> 4) & 15, p0 = tau >> 8;
+#pragma unroll
+        for (int s0 = 0; s0 < 16; ++s0) d[s0] = lds[e_slot(k1, r, p0, s0)];
+        if (p0) {
+            c32 tw[16];
+#pragma unroll
+            for (int s0 = 0; s0 < 16; ++s0) tw[s0] = w32<-1>(s0);     // conjugated inside: W32^(+s0)
+            dft16_tw<+1, true>(d, tw);
+        } else {
+            dft16<+1>(d);
+        }
+    }
+    FDAS_HD static void put_c_inv(int tau, const c32 *d, c32 *lds)
+    {
+        const int k1 = k1_of(tau), r = (tau >> 4) & 15, p0 = tau >> 8;
+#pragma unroll
+        for (int p1 = 0; p1 < 16; ++p1) lds[c_slot(k1, r, p0 + 2 * p1)] = d[p1];
     }
     FDAS_HD static void inv1(int tau, c32 *v, const c32 *lds, const c32 *tw1)
     {

@@ -122,7 +122,7 @@ class Plan:
     taps:     complex64 [M, K_max] (numpy, CPU or CUDA torch), zero beyond tap_len
     tap_len:  int32 [M] or None (all K_max)
     input_len: largest spectrum length that will be filtered
-    seg_fft:  segment transform length L in {1024, 2048, 4096}
+    seg_fft:  segment transform length L in {1024, 2048, 4096, 8192}
     precision: "fp32", or "fp16" / "bf16" for the mixed plans (16-bit input
                and template spectra, matrix-core inverse transforms, float32
                accumulation and power; L = 2048; convolve() and

@@ -42,14 +42,16 @@ def test_percentiles_pick_order_statistics():
     assert bench.percentiles([3.0]) == {"p10": 3.0, "median": 3.0, "p90": 3.0}
 
 
-def test_measured_traffic_tracks_kernel_source(monkeypatch):
-    # the committed L = 2048 summary was taken on the current kernel source
-    t = bench.measured_traffic(2048)
-    assert t is not None and 1.4e9 < t < 1.6e9
-    # a different source hash makes the figure unusable (reported as null)
+def test_measured_traffic_tracks_kernel_source(monkeypatch, tmp_path):
+    # a summary carrying the current source hash is used; any other hash,
+    # or no summary for the segment length, gives null
+    f = tmp_path / "traffic.md"
+    f.write_text(f"kernel_source_sha: {bench.kernel_source_hash()}\n\ntraffic_bytes_per_launch: 1.488765e+09\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {2048: str(f)})
+    assert bench.measured_traffic(2048) == 1.488765e9
+    assert bench.measured_traffic(1024) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.measured_traffic(2048) is None
-    assert bench.measured_traffic(8192) is None        # no summary for this length
 
 
 def test_more_than_one_gpu_is_refused():

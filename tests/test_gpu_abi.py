@@ -94,7 +94,7 @@ def test_call_errors(env):
     assert torch.count_nonzero(out).item() == 0      # nothing was launched
 
 
-@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("L", [1024, 2048, 4096, 8192])
 def test_segment_fft_against_dft(env, L):
     torch, fdas, _ = env
     _, bank = datagen.random_case(3, 4, 1, 9)
@@ -114,7 +114,7 @@ def test_segment_fft_against_dft(env, L):
     assert np.max(np.abs(back - xs)) <= 2e-6 * np.max(np.abs(xs))
 
 
-@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("L", [1024, 2048, 4096, 8192])
 def test_template_spectra_against_definition(env, L):
     torch, fdas, _ = env
     bank = datagen.make_bank(datagen.Z_SKA)

@@ -36,7 +36,7 @@ def cands_np(fdas, raw):
     return t.cpu().numpy(), b.cpu().numpy(), p.cpu().numpy()
 
 
-@pytest.mark.parametrize("L,k", [(1024, 16), (2048, 1), (2048, 32), (4096, 16)])
+@pytest.mark.parametrize("L,k", [(1024, 16), (2048, 1), (2048, 32), (4096, 16), (8192, 16)])
 def test_small_batches_against_oracle(env, L, k):
     torch, fdas = env
     x_all, bank = datagen.random_case(100 + L + k, 140000, 6, 47)

@@ -57,7 +57,7 @@ def compare(P, x_np, bank, n, rows_per_block=16, threads=0):
     return st
 
 
-@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("L", [1024, 2048, 4096, 8192])
 @pytest.mark.parametrize("method", ["convolve", "tdfir"])
 def test_toy_full_plane(torch_cuda, fdas, toy, L, method):
     _say(f"[toy] 9 x 2^16 L={L} {method}")
@@ -73,7 +73,7 @@ def test_toy_full_plane(torch_cuda, fdas, toy, L, method):
     assert toy.bank.z[t_best] == -6
 
 
-@pytest.mark.parametrize("L", [1024, 2048, 4096])
+@pytest.mark.parametrize("L", [1024, 2048, 4096, 8192])
 def test_ska_headline_full_plane(torch_cuda, fdas, L):
     """85 templates x 2^22 points at every segment length the bench's
     autotuner may pick: the launch the bench times, compared with the oracle
@@ -133,6 +133,8 @@ def test_ska_tdfir_full_plane(torch_cuda, fdas):
     (6, 9001, 3, 1024, 2048),     # K_max = L / 2
     (7, 20011, 1, 64, 4096),      # M = 1, prime length
     (8, 70001, 7, 77, 2048),      # ragged taps, several segments, ragged tail
+    (9, 30001, 3, 4096, 8192),    # K_max = L / 2 at the longest segment
+    (10, 8000, 2, 33, 8192),      # n shorter than one segment
 ])
 @pytest.mark.parametrize("method", ["convolve", "tdfir"])
 def test_edge_cases(torch_cuda, fdas, seed, n, m, k_max, L, method):
