@@ -149,9 +149,9 @@ __global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_topk_kernel(
                 __syncthreads();
                 th = s_thr;
             }
-            bool any = false;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) any |= (pw[m] >= 0.f && pw[m] >= th);
+            // some cell qualifies exactly when the item's maximum does: the
+            // maximum is one of the cells whenever it is not negative
+            const bool any = mx >= 0.f && mx >= th;
             if (__syncthreads_or(any)) {
                 float2 *cand = reinterpret_cast<float2 *>(bufA);    // free: pass 0' reads are done
 #pragma unroll

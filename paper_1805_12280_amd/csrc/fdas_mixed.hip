@@ -703,13 +703,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
             __syncthreads();
             th = s_thr;
         }
-        bool any = false;
-#pragma unroll
-        for (int gam = 0; gam < 4; ++gam)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int i = 0; i < 2; ++i) any |= (pw[gam][h][i] >= 0.f && pw[gam][h][i] >= th);
+        // some cell qualifies exactly when the item's maximum does
+        const bool any = mx >= 0.f && mx >= th;
         // (also the barrier after pass C's reads of bx and pass A's writes of cc)
         if (__syncthreads_or(any)) {
 #pragma unroll
