@@ -112,6 +112,43 @@ def test_full_batch_matches_plane_path(env, L):
             _say(f"[full batch L={L}] array {a} n={n} ok")
 
 
+def test_long_array_matches_plane_path(env):
+    """Batched top-16 of an array of 25 * 2^20 points (85 templates: 2.2e9
+    cells, bins past 2^24) beside a short one, against the top-16 of each
+    array's plane from fdas_convolve (near-tie rule) and the oracle at every
+    reported cell."""
+    torch, fdas = env
+    w = datagen.ska_workload(25 << 20)
+    n0, n1 = w.n, (1 << 20) + 777
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n0, seg_fft=2048)
+    xs = [w.x, np.ascontiguousarray(w.x[:n1])]
+    dev = [torch.from_numpy(v).cuda() for v in xs]
+    t, b, p = cands_np(fdas, plan.convolve_batched(dev, topk=16))
+    out = torch.empty((85, n0), dtype=torch.float32, device="cuda")
+    for a, x in enumerate(dev):
+        n = x.shape[0]
+        plan.convolve(x, out=out[:, :n])
+        vals, idx = torch.topk(out[:, :n], 40, dim=1)      # per row, then merged on the host
+        cand = sorted(((float(vv), r, int(ii)) for r in range(85) for vv, ii in zip(vals[r].tolist(), idx[r].tolist())),
+                      key=lambda c: (-c[0], c[1], c[2]))[:16]
+        scale, kth = cand[0][0], cand[-1][0]
+        plane_cells = {(c[1], c[2]): c[0] for c in cand}
+        got = {(int(t[a, r]), int(b[a, r])): float(p[a, r]) for r in range(16)}
+        for c, pv in got.items():
+            if c in plane_cells:
+                assert abs(pv - plane_cells[c]) <= 1e-6 * scale, (a, c)
+            else:
+                assert pv >= kth - FP32_TOL * scale, ("extra", a, c)
+        for c, pv in plane_cells.items():
+            if c not in got:
+                assert pv <= float(p[a, 15]) + FP32_TOL * scale, ("missing", a, c)
+        ref = oracle.power_at(xs[a], w.bank.taps, w.bank.tap_len, t[a], b[a])
+        assert np.max(np.abs(p[a] - ref)) <= FP32_TOL * float(ref.max())
+        _say(f"[long batch] array {a} n={n} ok, best bin {int(b[a, 0])}")
+    # the long array's chirps past bin 2^24 are found
+    assert any(int(bb) > (1 << 24) for bb in b[0])
+
+
 def test_graph_capture_replays(env):
     torch, fdas = env
     x_all, bank = datagen.random_case(7, 300000, 9, 33)
