@@ -259,6 +259,38 @@ def test_mixed_batched_equals_plane(torch_cuda, fdas, prec):
     plan.close()
 
 
+def test_mixed_batched_long_array(torch_cuda, fdas):
+    """FP16 plan, an array of 25 * 2^20 points (2.2e9 cells, bins past 2^24)
+    beside a short one: each batched top-16 is exactly the top-16 of the
+    array's 16-bit plane (per-row top-40 merged with the (P desc, t asc,
+    bin asc) order), and every reported power is within the 16-bit bar of
+    the oracle at that cell."""
+    torch = torch_cuda
+    w = datagen.ska_workload(25 << 20)
+    n0, n1 = w.n, (1 << 20) + 777
+    xs = [w.x, np.ascontiguousarray(w.x[:n1])]
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n0, seg_fft=2048, precision="fp16")
+    dev = [to16(torch, x, "fp16") for x in xs]
+    raw = plan.convolve_batched(dev, topk=16)
+    torch.cuda.synchronize()
+    t, b, p = fdas.split_candidates(raw)
+    t, b, p = t.cpu().numpy(), b.cpu().numpy(), p.cpu().numpy()
+    out = torch.empty((85, n0), dtype=torch.float32, device="cuda")
+    for a, x in enumerate(dev):
+        n = x.shape[0]
+        plan.convolve(x, out=out[:, :n])
+        vals, idx = torch.topk(out[:, :n], 40, dim=1)
+        want = sorted(((r, int(ii), float(vv)) for r in range(85) for vv, ii in zip(vals[r].tolist(), idx[r].tolist())),
+                      key=lambda c: (-c[2], c[0], c[1]))[:16]
+        got = [(int(t[a, r]), int(b[a, r]), float(p[a, r])) for r in range(16)]
+        _say(f"[mixed long batch] array {a} n={n}: top {got[0]}")
+        assert got == want, (a, got[:4], want[:4])
+        ref = oracle.power_at(xs[a], w.bank.taps, w.bank.tap_len, t[a], b[a])
+        assert np.max(np.abs(p[a] - ref)) <= MIXED_TOL * float(ref.max())
+    assert any(int(bb) > (1 << 24) for bb in b[0])
+    plan.close()
+
+
 def test_mixed_batched_against_oracle(torch_cuda, fdas):
     """FP16 batched candidates against the oracle's whole plane of each array
     (original complex64 input), at the 16-bit tolerance."""
