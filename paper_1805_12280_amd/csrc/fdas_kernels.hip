@@ -256,35 +256,74 @@ __global__ __launch_bounds__(TD_THREADS) void tdfir_kernel(
     // elements l0 + c, c < 15, l0 = TD_R tau + kp - kb - 7 = 8 q + 1 with
     // q = tau + kp / 8 - 1 - blk (kp is a multiple of 8), whose slots are
     // 9 q + 1 + c + (c + 1) / 8: a per-work-item base, 9 words lower per
-    // block, plus compile-time offsets.
+    // block, plus compile-time offsets.  Consecutive windows overlap: element
+    // c + 8 of block blk is element c of block blk - 1 (c < 7).  So each block
+    // reads only its 8 new elements, and reads them one block ahead: three
+    // 8-element buffers take the roles (this block's new elements, the
+    // previous block's, the next block's) in turn, three blocks per loop
+    // trip, so no register is copied.
     const int wb = 9 * (tau + kp / 8 - 1) + 1;
+    auto load_new = [&](int blk, c32 (&dst)[8]) {
+        const float *const wr = xr + wb - 9 * blk, *const wi = xi + wb - 9 * blk;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) dst[c] = mk(wr[c + (c + 1) / 8], wi[c + (c + 1) / 8]);
+    };
     for (int t = t_beg; t < t_end; ++t) {
         const c32 *const ht = hs + (t - t_beg) * kp;
         const int nblk = (tap_len[t] + 7) >> 3;
         c32 acc[TD_R];
 #pragma unroll
         for (int r = 0; r < TD_R; ++r) acc[r] = mk(0.f, 0.f);
-        // one block of 8 taps: y[i] += sum_{k in block} x[i-k] h[k]
-        for (int blk = 0; blk < nblk; ++blk) {
-            const float *const wr = xr + wb - 9 * blk, *const wi = xi + wb - 9 * blk;
-            c32 win[15];
+        // one block of 8 taps: y[i] += sum_{k in block} x[i-k] h[k], with the
+        // window's elements c < 8 in cur and c >= 8 in prev; the next block's
+        // new elements are read into nxt first (the last block re-reads its
+        // own, unused)
+        float4 hn[4];                       // the next block's 8 taps, two per 16-byte read
+        auto load_taps = [&](int blk) {
 #pragma unroll
-            for (int c = 0; c < 15; ++c) win[c] = mk(wr[c + (c + 1) / 8], wi[c + (c + 1) / 8]);
-            float4 h2[4];                   // the block's 8 taps, two per 16-byte read
+            for (int e = 0; e < 4; ++e) hn[e] = reinterpret_cast<const float4 *>(ht)[4 * blk + e];
+        };
+        auto step = [&](const c32 (&cur)[8], const c32 (&prev)[8], c32 (&nxt)[8], int blk) {
+            float4 h2[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) h2[e] = reinterpret_cast<const float4 *>(ht)[4 * blk + e];
+            for (int e = 0; e < 4; ++e) h2[e] = hn[e];
+            const int nb = blk + 1 < nblk ? blk + 1 : blk;
+            load_new(nb, nxt);
+            load_taps(nb);
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk) {
                 const c32 hk = (kk & 1) ? mk(h2[kk >> 1].z, h2[kk >> 1].w) : mk(h2[kk >> 1].x, h2[kk >> 1].y);
 #pragma unroll
                 for (int r = 0; r < TD_R; ++r) {
-                    const c32 xv = win[r - kk + 7];
+                    const int c = r - kk + 7;
+                    const c32 xv = c < 8 ? cur[c] : prev[c - 8];
                     acc[r].re = fmaf(xv.re, hk.re, acc[r].re);
                     acc[r].re = fmaf(-xv.im, hk.im, acc[r].re);
                     acc[r].im = fmaf(xv.re, hk.im, acc[r].im);
                     acc[r].im = fmaf(xv.im, hk.re, acc[r].im);
                 }
             }
+        };
+        c32 wa[8], wb8[8], wc[8];
+        if (nblk > 0) {
+            load_taps(0);
+            load_new(0, wa);                // block 0: elements c < 8
+            {                               // and c = 8..14 (the would-be block -1's new ones)
+                const float *const wr = xr + wb, *const wi = xi + wb;
+#pragma unroll
+                for (int c = 8; c < 15; ++c) wc[c - 8] = mk(wr[c + (c + 1) / 8], wi[c + (c + 1) / 8]);
+                wc[7] = mk(0.f, 0.f);
+            }
+        }
+        int blk = 0;
+        for (; blk + 3 <= nblk; blk += 3) {
+            step(wa, wc, wb8, blk);
+            step(wb8, wa, wc, blk + 1);
+            step(wc, wb8, wa, blk + 2);
+        }
+        if (blk < nblk) {
+            step(wa, wc, wb8, blk);
+            if (blk + 1 < nblk) step(wb8, wa, wc, blk + 1);
         }
         float *Pt = P + (int64_t)t * ld;
         const int64_t ib = i0 + TD_R * tau;
