@@ -201,37 +201,47 @@ def test_taps_on_device(torch_cuda, fdas, toy):
     assert np.array_equal(p_host.template_spectra(), p_dev.template_spectra())
 
 
-def test_plane_past_2g_elements_sampled(torch_cuda, fdas):
-    """85 templates x 25 * 2^20 points (a ragged number of segments): the
-    plane holds 2.2e9 elements (8.9 GB), so row offsets pass 2^31 elements
-    and 2^32 bytes.  Windows at the start, the middle, the end and around
-    each injected chirp, in rows spread over the bank and the chirps'
-    de-chirping rows, against the oracle: float32 FDFIR and TDFIR at the
-    1e-4 bar, the FP16 plan at 2e-3."""
-    from fdas_check import MIXED_TOL
-    torch = torch_cuda
+@pytest.fixture(scope="module")
+def large(torch_cuda):
+    """85 templates x 25 * 2^20 points (a ragged number of segments at every
+    L): the plane holds 2.2e9 elements (8.9 GB), so row offsets pass 2^31
+    elements and 2^32 bytes.  Oracle windows at the start, the middle, the
+    end and around each injected chirp, in rows spread over the bank and the
+    chirps' de-chirping rows."""
     w = datagen.ska_workload(25 << 20)
     n, m = w.n, w.bank.num_templates
     assert m * n > 2 ** 31
-    _say(f"[large] 85 x {n} sampled windows")
     rows = sorted({0, 21, 42, 63, m - 1} | {int(np.argmin(np.abs(w.bank.z + c.z0))) for c in w.chirps})
     wins = [(0, 4096), (n // 2 - 2048, n // 2 + 2048), (n - 4096, n)]
     wins += [(max(0, int(c.r0) - 2048), min(n, int(c.r0) + 2048)) for c in w.chirps]
     refs = [oracle.power(w.x, w.bank.taps, w.bank.tap_len, rows=rows, i0=a, i1=b) for a, b in wins]
     peak = max(float(r.max()) for r in refs)
-    x = torch.from_numpy(w.x).cuda()
-    out = torch.empty((m, n), dtype=torch.float32, device="cuda")
-    cases = [("fp32", "convolve", FP32_TOL), ("fp32", "tdfir", FP32_TOL), ("fp16", "convolve", MIXED_TOL)]
-    for prec, method, tol in cases:
-        plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=2048, precision=prec)
-        xin = x if prec == "fp32" else torch.view_as_real(x).to(plan.input_dtype()).contiguous()
-        out.fill_(-7.0)
-        getattr(plan, method)(xin, out=out)
-        torch.cuda.synchronize()
-        err = max(float(np.abs(out[rows, a:b].cpu().numpy() - r).max()) for (a, b), r in zip(wins, refs))
-        _say(f"  {prec} {method}: max err / sampled peak {err / peak:.3e}")
-        assert err <= tol * peak, (prec, method, err / peak)
-        plan.close()
+    x = torch_cuda.from_numpy(w.x).cuda()
+    out = torch_cuda.empty((m, n), dtype=torch_cuda.float32, device="cuda")
+    return w, rows, wins, refs, peak, x, out
+
+
+@pytest.mark.parametrize("prec,method,L", [
+    ("fp32", "convolve", 1024), ("fp32", "convolve", 2048), ("fp32", "convolve", 4096),
+    ("fp32", "convolve", 8192), ("fp32", "tdfir", 2048), ("fp16", "convolve", 2048), ("bf16", "convolve", 2048)])
+def test_plane_past_2g_elements_sampled(torch_cuda, fdas, large, prec, method, L):
+    """The large plane's sampled windows against the oracle: float32 FDFIR at
+    every segment length and TDFIR at the 1e-4 bar, the FP16 plan at 2e-3,
+    the BF16 plan within its regression bound."""
+    from fdas_check import BF16_BOUND, MIXED_TOL
+    torch = torch_cuda
+    w, rows, wins, refs, peak, x, out = large
+    tol = {"fp32": FP32_TOL, "fp16": MIXED_TOL, "bf16": BF16_BOUND}[prec]
+    _say(f"[large] 85 x {w.n} {prec} {method} L={L}")
+    plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=w.n, seg_fft=L, precision=prec)
+    xin = x if prec == "fp32" else torch.view_as_real(x).to(plan.input_dtype()).contiguous()
+    out.fill_(-7.0)
+    getattr(plan, method)(xin, out=out)
+    torch.cuda.synchronize()
+    err = max(float(np.abs(out[rows, a:b].cpu().numpy() - r).max()) for (a, b), r in zip(wins, refs))
+    _say(f"  max err / sampled peak {err / peak:.3e}")
+    assert err <= tol * peak, (prec, method, L, err / peak)
+    plan.close()
 
 
 @pytest.mark.parametrize("L", [1024, 2048])
