@@ -146,7 +146,9 @@ int oracle_power_at(const double *x, int64_t n, const double *taps, const int32_
 {
     if (!x || !taps || !tap_len || !t_idx || !i_idx || !out || n < 0 || K_max < 1) return -1;
     for (int64_t p = 0; p < npts; ++p)
-        if (t_idx[p] < 0 || t_idx[p] >= M || i_idx[p] < 0 || tap_len[t_idx[p]] > K_max) return -1;
+        if (t_idx[p] < 0 || t_idx[p] >= M || i_idx[p] < 0 || tap_len[t_idx[p]] < 0 ||
+            tap_len[t_idx[p]] > K_max)
+            return -1;
     set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < npts; ++p) {

@@ -111,6 +111,28 @@ def test_window_and_sampled_points_agree():
     assert rel_err(pts, full[t, i]) <= 1e-13
 
 
+def test_bad_arguments_are_rejected():
+    """Every entry point refuses a tap length outside [0, K_max] (negative
+    ones included) and an out-of-range row, point or window."""
+    x, bank = datagen.random_case(35, 300, 3, 12)
+    bad = bank.tap_len.copy()
+    bad[1] = -1
+    for fn in (lambda tl: oracle.power(x, bank.taps, tl), lambda tl: oracle.conv(x, bank.taps, tl),
+               lambda tl: oracle.power_at(x, bank.taps, tl, [1], [5])):
+        with pytest.raises(ValueError):
+            fn(bad)
+    big = bank.tap_len.copy()
+    big[0] = bank.taps.shape[1] + 1
+    with pytest.raises(ValueError):
+        oracle.power_at(x, bank.taps, big, [0], [5])
+    with pytest.raises(ValueError):
+        oracle.power_at(x, bank.taps, bank.tap_len, [3], [5])
+    with pytest.raises(ValueError):
+        oracle.power_at(x, bank.taps, bank.tap_len, [0], [-1])
+    with pytest.raises(ValueError):
+        oracle.power(x, bank.taps, bank.tap_len, rows=[0], i0=10, i1=5)
+
+
 def test_thread_count_does_not_change_result():
     x, bank = datagen.random_case(34, 20000, 3, 30)
     a = oracle.power(x, bank.taps, bank.tap_len, nthreads=1)
