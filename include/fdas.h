@@ -56,8 +56,8 @@ enum {
 /* ---- plan flags -------------------------------------------------------- */
 #define FDAS_FP32            0u          /* float32 storage and arithmetic */
 #define FDAS_TAPS_ON_DEVICE  (1u << 0)   /* `taps` and `tap_len` are device pointers */
-#define FDAS_FP16            (1u << 1)   /* 16-bit IEEE storage, matrix-core inverse FFT */
-#define FDAS_BF16            (1u << 2)   /* bfloat16 storage, matrix-core inverse FFT */
+#define FDAS_FP16            (1u << 1)   /* binary16 input, matrix-core inverse FFT */
+#define FDAS_BF16            (1u << 2)   /* bfloat16 input, matrix-core inverse FFT */
 
 typedef struct fdas_plan fdas_plan;
 
@@ -96,13 +96,17 @@ typedef struct {
  *              workgroup; a device that has less returns FDAS_EUNSUPPORTED.
  *   flags      FDAS_FP32, FDAS_FP16 or FDAS_BF16, optionally |
  *              FDAS_TAPS_ON_DEVICE; anything else returns FDAS_EUNSUPPORTED.
- *              FDAS_FP16/FDAS_BF16 ("mixed" plans): the input spectrum and the
- *              template spectra are stored in 16 bits (round to nearest even;
- *              the spectra scaled by a power of two so their largest
- *              component is in [1/2, 1)); the forward FFT runs in float32 and
- *              the inverse FFT passes run on the matrix cores with 16-bit
- *              operands and float32 accumulation, each segment scaled by a
- *              power of two; the power plane is float32.  Mixed plans need
+ *              FDAS_FP16/FDAS_BF16 ("mixed" plans): the input spectrum is
+ *              given as binary16 or bfloat16 pairs; the forward FFT runs in
+ *              float32; the inverse FFT passes run on the matrix cores with
+ *              binary16 operands and float32 accumulation, each segment
+ *              scaled by a power of two (the 5 exponent bits then suffice,
+ *              and binary16 keeps 11 significant bits against bfloat16's 8);
+ *              the power plane is float32.  The template spectra (scaled by a
+ *              power of two so their largest component is in [1/2, 1)) are
+ *              stored as binary16 for FDAS_FP16, where Z = X H is formed in
+ *              packed binary16 arithmetic, and as float32 for FDAS_BF16, where
+ *              Z = X H is formed in float32 and rounded once.  Mixed plans need
  *              seg_fft = 2048 (or 0) and support fdas_convolve and
  *              fdas_convolve_batched; fdas_tdfir and fdas_segment_fft
  *              return FDAS_EUNSUPPORTED.  A mixed plan also
@@ -259,7 +263,12 @@ int fdas_plan_template_spectra(const fdas_plan *plan, void *host_out);
 /* fdas_plan_info -- geometry and footprint of a plan (host struct, not NULL). */
 int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out);
 
-/* fdas_plan_destroy -- wait for the device, free the plan.  NULL is a no-op. */
+/*
+ * fdas_plan_destroy -- wait for the work the plan's calls enqueued (on every
+ * stream a call used, the last such work; other work on the device is not
+ * waited for), then free the plan.  Calls captured into a HIP graph are not
+ * tracked: the caller finishes the graph's replays first.  NULL is a no-op.
+ */
 void fdas_plan_destroy(fdas_plan *plan);
 
 /* Static text for a status code. */

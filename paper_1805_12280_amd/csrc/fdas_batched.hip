@@ -216,8 +216,7 @@ __global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_topk_kernel(
 // (each sorted best first) by K rounds of a workgroup-wide argmax of the list
 // heads.  Each of the nb workgroups of the first kernel wrote at most one
 // list per array; work-item tid owns workgroups tid, tid + 256, ...
-constexpr int MERGE_THREADS = 256;
-constexpr int MERGE_Q = 8;           // lists per work-item: nb <= 2048
+// (MERGE_THREADS, MERGE_Q: fdas_args.h; nb <= MERGE_MAX_LISTS)
 
 __global__ __launch_bounds__(MERGE_THREADS) void topk_merge_kernel(
     const Cand *__restrict__ stage, const int2 *__restrict__ hdr, const int *__restrict__ nslots,
@@ -345,7 +344,7 @@ hipError_t launch_topk(const TopkArgs &a, hipStream_t st)
 hipError_t launch_topk_merge(const void *stage, const void *hdr, const int *nslots, int nb, int max_slots,
                              int K, int count, void *out, hipStream_t st)
 {
-    if (nb > MERGE_THREADS * MERGE_Q) return hipErrorInvalidValue;
+    if (nb > MERGE_MAX_LISTS) return hipErrorInvalidValue;   // excluded by batch_shape
     hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)count), dim3(MERGE_THREADS), 0, st,
                        (const Cand *)stage, (const int2 *)hdr, nslots, nb, max_slots, K, (Cand *)out);
     return hipGetLastError();

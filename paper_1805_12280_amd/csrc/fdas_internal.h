@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fdas_args.h"
+
 namespace fdas {
 
 struct c32;
@@ -44,18 +46,6 @@ struct TdArgs {
     int64_t ld;
 };
 
-constexpr int MAX_BATCH = 128;              // FDAS_MAX_BATCH
-constexpr int TOPK_MAX = 32;                // FDAS_MAX_TOPK
-
-// Arrays of one batched call, passed by value as a kernel argument (so a
-// captured graph holds it without any copy node).
-struct BatchSet {
-    const c32 *x[MAX_BATCH];
-    int64_t n[MAX_BATCH];
-    int64_t item_begin[MAX_BATCH + 1];    // first item of each array; [count] = total
-    int count;
-};
-
 // One candidate cell (same layout as fdas_cand) and the order of cells:
 // power descending, then template ascending, then bin ascending (a strict
 // total order, since (template, bin) is unique).
@@ -86,7 +76,7 @@ struct TopkArgs {
 struct MixedArgs {
     const void *x;        // 16-bit complex [n]
     int64_t n;
-    const void *H16;      // 16-bit complex [M][2048], pass-A lane order
+    const void *H16;      // template spectra [M][2048], pass-A lane order (mixed_spectra_bytes)
     const void *mat;      // DFT matrices of the three passes (mixed_matrix_bytes())
     const c32 *twL;
     int M, D, V, eh;
@@ -110,11 +100,11 @@ size_t fused_lds_bytes(int L);              // LDS of the float32 template-loop 
 int tdfir_group(int kp, int M);              // largest template group whose taps fit TD_TAP_BYTES
 int topk_blocks_per_cu(int L);
 hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
-                            uint32_t *H16, hipStream_t st);
+                            void *H16, hipStream_t st);
+size_t mixed_spectra_bytes(bool bf, int M);  // template spectra of a 16-bit plan
 int mixed_blocks_per_cu(bool bf);
 size_t mixed_matrix_bytes();
-size_t mixed_stage_bytes(int64_t segments);
-hipError_t launch_mat_table(bool bf, void *tab, hipStream_t st);
+hipError_t launch_mat_table(void *tab, hipStream_t st);
 hipError_t launch_mixed(const MixedArgs &a, hipStream_t st);
 hipError_t launch_topk(const TopkArgs &a, hipStream_t st);
 // merge of the per-workgroup candidate lists of each array (second kernel

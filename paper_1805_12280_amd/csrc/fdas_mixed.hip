@@ -1,6 +1,14 @@
-// fdas_mixed.hip -- the overlap-save hot path with 16-bit storage and the
-// inverse segment transforms on the matrix cores (FP16 or BF16 operands,
-// FP32 accumulation).  L = 2048.
+// fdas_mixed.hip -- the overlap-save hot path with 16-bit storage of the
+// input spectrum (binary16 or bfloat16) and the inverse segment transforms on
+// the matrix cores (binary16 operands, FP32 accumulation).  L = 2048.
+//
+// Both plans feed the matrix cores binary16 operands: each segment is scaled
+// by a power of two, so the 5 exponent bits of binary16 suffice and its 11
+// significant bits keep 3 more than bfloat16's 8.  An FP16 plan stores the
+// template spectra as binary16 and forms Z = X H in packed binary16
+// arithmetic; a BF16 plan (bfloat16 input) keeps the template spectra in
+// float32 and forms Z = X H in float32, rounding it once to binary16, so the
+// arithmetic adds no more than one 11-bit rounding per operand of each pass.
 //
 // Two launches per call.  Per segment (mixed_fwd_kernel, float32 VALU):
 // gather the 16-bit input, forward FFT (seg_fft.h), redistribute the
@@ -82,42 +90,49 @@ template <> struct Half<false> {   // IEEE binary16
     __device__ static uint32_t twmul(float re, float im, TwReg w) { return cmulp(pack_acc(re, im), w); }
 };
 
-template <> struct Half<true> {    // bfloat16
-    __device__ static uint32_t pack(float re, float im)
+// The loop policy of a plan whose input is bfloat16: the same binary16
+// operands, matrix products and packed twiddle products as an FP16 plan, with
+// the template spectra held in float32 (ZW = c32 per value) and Z = X H
+// formed in float32 from the binary16-staged X, then rounded once.
+template <> struct Half<true> : Half<false> {
+    __device__ static uint32_t zmul(XReg x, c32 h)
     {
-        b2v v = {(__bf16)re, (__bf16)im};       // round to nearest even
-        return __builtin_bit_cast(uint32_t, v);
+        const c32 xv = Half<false>::unpack(x);
+        const c32 z = mul(xv, h);
+        return Half<false>::pack(z.re, z.im);
     }
-    __device__ static uint32_t pack_acc(float re, float im) { return pack(re, im); }
+};
+
+// Input formats: a complex value as a pair of 16-bit numbers in one word.
+template <bool BF> struct In16;
+template <> struct In16<false> {
+    __device__ static c32 unpack(uint32_t w) { return Half<false>::unpack(w); }
+};
+template <> struct In16<true> {
     __device__ static c32 unpack(uint32_t w)
     {
         return mk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
     }
-    __device__ static f4v mma16(uint2 a, uint2 b, f4v c)
+};
+
+// Template spectra of one work-item for one template, in the order pass A
+// consumes them (16 values): packed binary16 for an FP16 plan, float32 for a
+// BF16 plan.
+template <bool BF> struct HSpec;
+template <> struct HSpec<false> {
+    uint4 q[4];
+    __device__ __forceinline__ uint32_t at(int v) const { return (&q[v >> 2].x)[v & 3]; }
+};
+template <> struct HSpec<true> {
+    float4 q[8];
+    __device__ __forceinline__ c32 at(int v) const
     {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0, 0, 0);
-    }
-    __device__ static f4v mma32(uint4 a, uint4 b, f4v c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0, 0);
-    }
-    // no packed bfloat16 arithmetic: the products run in float32 and are
-    // rounded once
-    using XReg = c32;
-    using TwReg = c32;
-    __device__ static XReg to_x(float re, float im) { return mk(re, im); }
-    __device__ static TwReg to_tw(float re, float im) { return mk(re, im); }
-    __device__ static uint32_t zmul(XReg x, uint32_t h)
-    {
-        const c32 z = mul(x, unpack(h));
-        return pack(z.re, z.im);
-    }
-    __device__ static uint32_t twmul(float re, float im, TwReg w)
-    {
-        const c32 y = mul(mk(re, im), w);
-        return pack(y.re, y.im);
+        const float4 f = q[v >> 1];
+        return (v & 1) ? mk(f.z, f.w) : mk(f.x, f.y);
     }
 };
+// bytes of one template spectrum value
+constexpr int hspec_bytes(bool bf) { return bf ? 8 : 4; }
 
 // One real matrix entry of exp(2 pi i turns) for interleaved rows/columns.
 __device__ __forceinline__ float wentry(int row, int k, double turns)
@@ -139,7 +154,7 @@ __device__ __forceinline__ float wentry(int row, int k, double turns)
 
 template <bool BF>
 __global__ void tspec_mix_kernel(const c32 *__restrict__ taps, const int *__restrict__ tap_len, int kp, int M,
-                                 float scale, uint32_t *__restrict__ H16)
+                                 float scale, void *__restrict__ H16)
 {
     using namespace mix;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,7 +173,10 @@ __global__ void tspec_mix_kernel(const c32 *__restrict__ taps, const int *__rest
         re += hr * c - hi * s;
         im += hr * s + hi * c;
     }
-    H16[idx] = Half<BF>::pack((float)(re / L * scale), (float)(im / L * scale));
+    if constexpr (BF)
+        reinterpret_cast<c32 *>(H16)[idx] = mk((float)(re / L * scale), (float)(im / L * scale));
+    else
+        reinterpret_cast<uint32_t *>(H16)[idx] = Half<false>::pack((float)(re / L * scale), (float)(im / L * scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -173,7 +191,6 @@ constexpr int MAT_D = MAT_A_UINT2 / 2;         // in uint4 units
 constexpr int MAT_UINT4 = MAT_D + 2 * 64;
 constexpr size_t MAT_BYTES = MAT_UINT4 * sizeof(uint4);
 
-template <bool BF>
 __global__ void mat_table_kernel(uint4 *__restrict__ tab)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -185,7 +202,7 @@ __global__ void mat_table_kernel(uint4 *__restrict__ tab)
             const int k = 4 * g + e;
             e4[e] = wentry(i, k, mix::turns_A(r, i >> 1, k >> 1));
         }
-        reinterpret_cast<uint2 *>(tab)[idx] = make_uint2(Half<BF>::pack(e4[0], e4[1]), Half<BF>::pack(e4[2], e4[3]));
+        reinterpret_cast<uint2 *>(tab)[idx] = make_uint2(Half<false>::pack(e4[0], e4[1]), Half<false>::pack(e4[2], e4[3]));
     } else if (idx < MAT_A_UINT2 + 2 * 64) {
         const int h = (idx - MAT_A_UINT2) >> 6, out = 8 * h + (i >> 1);
         float e8[8];
@@ -193,8 +210,8 @@ __global__ void mat_table_kernel(uint4 *__restrict__ tab)
             const int k = 8 * g + e;
             e8[e] = wentry(i, k, mix::turns_D16(out, k >> 1));
         }
-        tab[MAT_D + h * 64 + l] = make_uint4(Half<BF>::pack(e8[0], e8[1]), Half<BF>::pack(e8[2], e8[3]),
-                                             Half<BF>::pack(e8[4], e8[5]), Half<BF>::pack(e8[6], e8[7]));
+        tab[MAT_D + h * 64 + l] = make_uint4(Half<false>::pack(e8[0], e8[1]), Half<false>::pack(e8[2], e8[3]),
+                                             Half<false>::pack(e8[4], e8[5]), Half<false>::pack(e8[6], e8[7]));
     }
 }
 
@@ -214,7 +231,6 @@ __device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16,
                                                float *__restrict__ ps)
 {
     using SG = Seg<2048>;
-    using HF = Half<BF>;
     constexpr int L = mix::L, T = mix::T;
     // One LDS buffer serves both exchanges and the redistribution (2176
     // slots of 17 per 16 frequencies), one barrier more than two buffers but
@@ -232,7 +248,7 @@ __device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16,
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int j = tau + T * m;
-            v[m] = (j >= lo && j < hi) ? HF::unpack(xs[j]) : mk(0.f, 0.f);
+            v[m] = (j >= lo && j < hi) ? In16<BF>::unpack(xs[j]) : mk(0.f, 0.f);
         }
     }
     {
@@ -330,11 +346,10 @@ template <bool BF> struct MixLane {
     }
     // pass A, column set r = 8w + gam: Z = X H rounded once, radix 8 over s;
     // returns c[2g][col][r] and c[2g + 1][col][r] packed
-    __device__ __forceinline__ void pass_a(const typename HF::XReg (&X)[16], const uint4 (&Hn)[4], int gam,
+    __device__ __forceinline__ void pass_a(const typename HF::XReg (&X)[16], const HSpec<BF> &Hn, int gam,
                                            uint32_t &c0, uint32_t &c1) const
     {
-        const uint32_t hw0 = (&Hn[gam >> 1].x)[(gam & 1) * 2], hw1 = (&Hn[gam >> 1].x)[(gam & 1) * 2 + 1];
-        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], hw0), HF::zmul(X[2 * gam + 1], hw1));
+        const uint2 bop = make_uint2(HF::zmul(X[2 * gam], Hn.at(2 * gam)), HF::zmul(X[2 * gam + 1], Hn.at(2 * gam + 1)));
         const f4v d = HF::mma16(aA[gam], bop, f4v{0.f, 0.f, 0.f, 0.f});
         c0 = HF::pack_acc(d[0], d[1]);
         c1 = HF::pack_acc(d[2], d[3]);
@@ -400,12 +415,18 @@ struct MixBases {
     }
 };
 
-// template spectra of template t for work-item tau (16 packed values)
-__device__ __forceinline__ void load_h16(const uint32_t *__restrict__ H16, int t, int tau, uint4 (&Hn)[4])
+// template spectra of template t for work-item tau (its 16 values, contiguous)
+__device__ __forceinline__ void load_h16(const void *__restrict__ H16, int t, int tau, HSpec<false> &Hn)
 {
-    const uint4 *Ht = reinterpret_cast<const uint4 *>(H16 + (int64_t)t * mix::L) + tau * 4;
+    const uint4 *Ht = reinterpret_cast<const uint4 *>(H16) + ((int64_t)t * mix::L + tau * 16) / 4;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Hn[k] = Ht[k];
+    for (int k = 0; k < 4; ++k) Hn.q[k] = Ht[k];
+}
+__device__ __forceinline__ void load_h16(const void *__restrict__ H16, int t, int tau, HSpec<true> &Hn)
+{
+    const float4 *Ht = reinterpret_cast<const float4 *>(H16) + ((int64_t)t * mix::L + tau * 16) / 2;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Hn.q[k] = Ht[k];
 }
 
 // staged spectrum of global segment s for work-item tau
@@ -430,7 +451,7 @@ __device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t 
 // vector work of the other.
 template <bool BF>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_kernel(
-    const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const uint32_t *__restrict__ H16,
+    const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const void *__restrict__ H16,
     const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int64_t items,
     float *__restrict__ P, int64_t ld)
 {
@@ -464,7 +485,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     int t = (int)(u0 - s * M);
     int64_t sa = s;                    // segment and template of the pass-A item
     int ta = t;
-    uint4 Hn[4];                       // template spectra of the pass-A item
+    HSpec<BF> Hn;                      // template spectra of the pass-A item
     typename HF::XReg X[16];           // sigma-scaled spectrum of segment sa at zq(w, l, v)
     // advance the pass-A item; its template spectra are in flight from here on
     auto next_a = [&]() {
@@ -571,7 +592,7 @@ __global__ __launch_bounds__(128) void mixed_fwd_batch_kernel(BatchSet bs, int M
 // measured 5% faster; BF16, whose products stay in float32, runs best at 2)
 template <bool BF>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3))) void fdfir_mixed_topk_kernel(
-    BatchSet bs, const float4 *__restrict__ Xs, const float *__restrict__ ps, const uint32_t *__restrict__ H16,
+    BatchSet bs, const float4 *__restrict__ Xs, const float *__restrict__ ps, const void *__restrict__ H16,
     const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int K, int64_t items,
     Cand *__restrict__ stage, int2 *__restrict__ hdr, int *__restrict__ nslots, int max_slots)
 {
@@ -611,7 +632,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
     // the pass-A item u + 1 runs one phase ahead
     int64_t gsa = gs;
     int ta = t;
-    uint4 Hn[4];
+    HSpec<BF> Hn;
     typename HF::XReg X[16];
     auto next_a = [&]() {
         if (++ta == M) { ta = 0; ++gsa; }
@@ -774,16 +795,17 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
 
 size_t mixed_matrix_bytes() { return MAT_BYTES; }
 
-hipError_t launch_mat_table(bool bf, void *tab, hipStream_t st)
+hipError_t launch_mat_table(void *tab, hipStream_t st)
 {
     const dim3 grid((MAT_A_UINT2 + 2 * 64 + 255) / 256), blk(256);
-    if (bf) hipLaunchKernelGGL(mat_table_kernel<true>, grid, blk, 0, st, (uint4 *)tab);
-    else hipLaunchKernelGGL(mat_table_kernel<false>, grid, blk, 0, st, (uint4 *)tab);
+    hipLaunchKernelGGL(mat_table_kernel, grid, blk, 0, st, (uint4 *)tab);
     return hipGetLastError();
 }
 
+size_t mixed_spectra_bytes(bool bf, int M) { return (size_t)hspec_bytes(bf) * (size_t)M * mix::L; }
+
 hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
-                            uint32_t *H16, hipStream_t st)
+                            void *H16, hipStream_t st)
 {
     const int64_t total = (int64_t)M * mix::L;
     dim3 grid((unsigned)((total + 255) / 256)), blk(256);
@@ -815,13 +837,13 @@ hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st)
     const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
     if (a.bf) {
         hipLaunchKernelGGL(mixed_fwd_batch_kernel<true>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs, ps);
-        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<true>, gi, blk, 0, st, *a.bs, Xs, ps, (const uint32_t *)a.H16,
+        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<true>, gi, blk, 0, st, *a.bs, Xs, ps, a.H16,
                            a.twL, (const uint4 *)a.mat, a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage,
                            (int2 *)a.hdr, a.nslots, a.max_slots);
     } else {
         hipLaunchKernelGGL(mixed_fwd_batch_kernel<false>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs,
                            ps);
-        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<false>, gi, blk, 0, st, *a.bs, Xs, ps, (const uint32_t *)a.H16,
+        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<false>, gi, blk, 0, st, *a.bs, Xs, ps, a.H16,
                            a.twL, (const uint4 *)a.mat, a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage,
                            (int2 *)a.hdr, a.nslots, a.max_slots);
     }
@@ -830,7 +852,7 @@ hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st)
     return launch_topk_merge(a.stage, a.hdr, a.nslots, (int)a.grid, a.max_slots, a.K, a.bs->count, a.out, st);
 }
 
-size_t mixed_stage_bytes(int64_t segments) { return (size_t)segments * (mix::L * sizeof(c32) + sizeof(float)); }
+static_assert(mix::L == MIXED_L, "staging size of the 16-bit plans (mixed_stage_bytes)");
 
 hipError_t launch_mixed(const MixedArgs &a, hipStream_t st)
 {
@@ -841,12 +863,12 @@ hipError_t launch_mixed(const MixedArgs &a, hipStream_t st)
     if (a.bf) {
         hipLaunchKernelGGL(mixed_fwd_kernel<true>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,
                            a.eh, Xs, ps);
-        hipLaunchKernelGGL(fdfir_mixed_kernel<true>, gi, blk, 0, st, Xs, ps, a.n, (const uint32_t *)a.H16, a.twL,
+        hipLaunchKernelGGL(fdfir_mixed_kernel<true>, gi, blk, 0, st, Xs, ps, a.n, a.H16, a.twL,
                            (const uint4 *)a.mat, a.M, a.D, a.V, a.items, a.P, a.ld);
     } else {
         hipLaunchKernelGGL(mixed_fwd_kernel<false>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,
                            a.eh, Xs, ps);
-        hipLaunchKernelGGL(fdfir_mixed_kernel<false>, gi, blk, 0, st, Xs, ps, a.n, (const uint32_t *)a.H16, a.twL,
+        hipLaunchKernelGGL(fdfir_mixed_kernel<false>, gi, blk, 0, st, Xs, ps, a.n, a.H16, a.twL,
                            (const uint4 *)a.mat, a.M, a.D, a.V, a.items, a.P, a.ld);
     }
     return hipGetLastError();

@@ -110,6 +110,15 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _on_stream(stream):
+    """Context in which torch allocates buffers for a call enqueued on
+    `stream` (None: the current stream), so the caching allocator does not
+    hand their memory out again while that stream may still use it."""
+    import contextlib
+    import torch
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
+
+
 def split_candidates(raw):
     """(t, bin, p) views of a [count, topk, 3] candidate tensor."""
     import torch
@@ -200,7 +209,7 @@ class Plan:
         import torch
         return {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}[self.precision]
 
-    def _io(self, x, out):
+    def _io(self, x, out, stream=None):
         import torch
         if self.precision == "fp32":
             if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64):
@@ -214,7 +223,8 @@ class Plan:
                 raise FdasError(FDAS_EINVAL, f"x must be a contiguous CUDA {want} tensor [n, 2] (re, im)")
         n = x.shape[0]
         if out is None:
-            out = torch.empty((self.num_templates, n), dtype=torch.float32, device=x.device)
+            with _on_stream(stream):
+                out = torch.empty((self.num_templates, n), dtype=torch.float32, device=x.device)
         if out.dtype != torch.float32 or not out.is_cuda or out.dim() != 2 or out.stride(1) != 1 \
                 or out.shape[0] != self.num_templates or out.shape[1] < n:
             raise FdasError(FDAS_EINVAL, "out must be CUDA float32 [M, >=n] with unit column stride")
@@ -222,14 +232,14 @@ class Plan:
 
     def convolve(self, x, out=None, stream=None):
         """Power plane P[t, i] = |sum_k x[i-k] h_t[k]|^2 via overlap-save FDFIR."""
-        n, out = self._io(x, out)
+        n, out = self._io(x, out, stream)
         check(self._lib.fdas_convolve(self._h, _ptr(x), n, _ptr(out), out.stride(0),
                                       _stream_handle(stream)))
         return out
 
     def tdfir(self, x, out=None, stream=None):
         """The same power plane by direct time-domain FIR."""
-        n, out = self._io(x, out)
+        n, out = self._io(x, out, stream)
         check(self._lib.fdas_tdfir(self._h, _ptr(x), n, _ptr(out), out.stride(0),
                                    _stream_handle(stream)))
         return out
@@ -266,10 +276,11 @@ class Plan:
         lengths = [x.shape[0] for x in xs]
         need = self.batched_workspace_bytes(lengths, topk)
         dev = xs[0].device
-        if workspace is None:
-            workspace = torch.empty(need, dtype=torch.uint8, device=dev)
-        if out is None:
-            out = torch.empty((count, topk, 3), dtype=torch.int32, device=dev)
+        with _on_stream(stream):
+            if workspace is None:
+                workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+            if out is None:
+                out = torch.empty((count, topk, 3), dtype=torch.int32, device=dev)
         if out.dtype != torch.int32 or tuple(out.shape) != (count, topk, 3) or not out.is_contiguous():
             raise FdasError(FDAS_EINVAL, "out must be a contiguous int32 [count, topk, 3] tensor")
         ptrs = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
@@ -284,7 +295,8 @@ class Plan:
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64
                 and x.dim() == 2 and x.shape[1] == self.seg_fft and x.is_contiguous()):
             raise FdasError(FDAS_EINVAL, "x must be CUDA complex64 [count, L], contiguous")
-        out = torch.empty_like(x)
+        with _on_stream(stream):
+            out = torch.empty_like(x)
         check(self._lib.fdas_segment_fft(self._h, _ptr(x), _ptr(out), x.shape[0], int(direction),
                                          _stream_handle(stream)))
         return out

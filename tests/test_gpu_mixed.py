@@ -1,25 +1,31 @@
 """GPU parity of the 16-bit plans (FP16 / BF16 storage of the input and the
 template spectra, inverse segment transforms on the matrix cores with FP32
-accumulation) against the FP64 oracle on the ORIGINAL complex64 input.
+accumulation) against the FP64 oracle.
 
-Bar: max |P_gpu - P_ref| / max P_ref <= 2e-3 per input array and the same
-top-16 cells up to the near-tie rule at that tolerance, for FP16.  BF16
-keeps 8 significant bits: rounding the stored input alone moves the power
-by more than 2e-3 of the peak, so BF16 misses that bar by construction; its
-tests hold it to BF16_BOUND, a regression guard, and print the measured
-value."""
+Two comparisons per case, both against the oracle (Eq. (1) and the power of
+Section 4.3 in float64):
+- on the ORIGINAL complex64 input: the acceptance figure, which includes the
+  rounding of the stored input;
+- on the input AS STORED (rounded to 16 bits, upcast exactly): what remains
+  is the kernel's own error.
+Bars: the kernel's own error <= 2e-3 of the peak power for both formats.
+FP16 also meets 2e-3 on the original input, with the same top-16 cells up to
+the near-tie rule.  BF16 keeps 8 significant bits, and rounding the input
+alone moves the power by more than 2e-3 of the peak on the headline input
+(the CPU test tests/test_precision_floor.py pins that floor); its total is
+held to that case's floor (the oracle on the stored input against the oracle
+on the original) plus the 2e-3 kernel bar, which bounds it by the triangle
+inequality."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
-from fdas_check import MIXED_TOL, BF16_BOUND, PlaneStats
+from fdas_check import MIXED_TOL, PlaneStats
 from paper_1805_12280_amd import datagen
 
 pytestmark = pytest.mark.gpu
-
-BAR = {"fp16": MIXED_TOL, "bf16": BF16_BOUND}
 
 
 def _say(*a):
@@ -62,14 +68,48 @@ def run16(torch, plan, x_np, prec, ld=None):
     return out.cpu().numpy()
 
 
-def compare(P, x_np, bank, n, rows_per_block=16):
-    st = PlaneStats()
+def stored(torch, x_np, prec):
+    """The input as a 16-bit plan stores it, upcast exactly to complex64."""
+    v = to16(torch, x_np, prec).float().cpu().numpy()
+    return (v[:, 0].astype(np.float64) + 1j * v[:, 1]).astype(np.complex64)
+
+
+class Three:
+    """GPU plane against the oracle on the original input (total), against
+    the oracle on the stored input (the kernel's own error), and the two
+    oracle planes against each other (the input-rounding floor)."""
+
+    def __init__(self):
+        self.total, self.own, self.floor = PlaneStats(), PlaneStats(), PlaneStats()
+
+    def add(self, rows, P_rows, ref, ref_stored):
+        self.total.add(rows, P_rows, ref)
+        self.own.add(rows, P_rows, ref_stored)
+        self.floor.add(rows, ref_stored, ref)
+
+    def check(self, prec, label=""):
+        t, o, f = self.total.norm_err, self.own.norm_err, self.floor.norm_err
+        _say(f"  {label}{prec}: total {t:.3e} (rrmse {self.total.rrmse:.2e}), kernel's own {o:.3e}, "
+             f"input-rounding floor {f:.3e}")
+        assert o <= MIXED_TOL, ("kernel's own error", prec, o)
+        ok, bad = self.own.topk_agree(MIXED_TOL)
+        assert ok, bad
+        bar = MIXED_TOL if prec == "fp16" else f + MIXED_TOL * self.own.max_ref / max(self.total.max_ref, 1e-300)
+        assert t <= bar, ("total error", prec, t, bar)
+        ok, bad = self.total.topk_agree(bar)
+        assert ok, bad
+
+
+def compare3(torch, P, x_np, prec, bank, n, rows_per_block=16):
+    th = Three()
+    xs = stored(torch, x_np[:n], prec)
     m = bank.num_templates
     for r0 in range(0, m, rows_per_block):
         rows = list(range(r0, min(m, r0 + rows_per_block)))
         ref = oracle.power(x_np[:n], bank.taps, bank.tap_len, rows=rows)
-        st.add(rows, P[rows, :n], ref)
-    return st
+        ref_s = oracle.power(xs, bank.taps, bank.tap_len, rows=rows)
+        th.add(rows, P[rows, :n], ref, ref_s)
+    return th
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -89,16 +129,7 @@ def test_mixed_cases(torch_cuda, fdas, prec, seed, n, m, k_max):
     assert plan.seg_fft == 2048 and plan.variant == f"fused-ols-mfma-{prec}"
     P = run16(torch_cuda, plan, x, prec, ld=n + 3)
     assert np.all(P[:, n:] == -7.0), "wrote beyond n"
-    st = compare(P, x, bank, n)
-    # the same against the input as stored (rounded to 16 bits, upcast
-    # exactly): what remains is the kernel's own rounding
-    xr = to16(torch_cuda, x, prec).float().cpu().numpy()
-    xr = (xr[:, 0].astype(np.float64) + 1j * xr[:, 1]).astype(np.complex64)
-    st_r = compare(P, xr, bank, n)
-    _say(st.summary(), "| vs stored input:", f"{st_r.norm_err:.3e}")
-    assert st.norm_err <= BAR[prec]
-    ok, bad = st.topk_agree(BAR[prec])
-    assert ok, bad
+    compare3(torch_cuda, P, x, prec, bank, n).check(prec)
     plan.close()
 
 
@@ -107,12 +138,9 @@ def test_mixed_toy(torch_cuda, fdas, toy, prec):
     _say(f"[mixed toy] 9 x 2^16 {prec}")
     plan = fdas.Plan(toy.bank.taps, toy.bank.tap_len, input_len=toy.n, seg_fft=2048, precision=prec)
     P = run16(torch_cuda, plan, toy.x, prec)
-    st = compare(P, toy.x, toy.bank, toy.n)
-    _say(st.summary())
-    assert st.norm_err <= BAR[prec]
-    ok, bad = st.topk_agree(BAR[prec])
-    assert ok, bad
-    t_best, _, _ = st.topk("gpu")[0]
+    th = compare3(torch_cuda, P, toy.x, prec, toy.bank, toy.n)
+    th.check(prec)
+    t_best, _, _ = th.total.topk("gpu")[0]
     assert toy.bank.z[t_best] == -6
 
 
@@ -128,17 +156,16 @@ def test_mixed_ska_full_plane(torch_cuda, fdas, prec):
     out = torch.empty((85, w.n), dtype=torch.float32, device="cuda")
     plan.convolve(x, out=out)
     torch.cuda.synchronize()
-    st = PlaneStats()
+    th = Three()
+    xs = stored(torch, w.x, prec)
     for r0 in range(0, 85, 17):
         rows = list(range(r0, r0 + 17))
         ref = oracle.power(w.x, w.bank.taps, w.bank.tap_len, rows=rows)
-        st.add(rows, out[r0:r0 + 17].cpu().numpy(), ref)
-        _say(f"  rows {r0}..{r0 + 16}: norm_err so far {st.norm_err:.3e}")
-    _say(st.summary())
-    assert st.norm_err <= BAR[prec]
-    ok, bad = st.topk_agree(BAR[prec])
-    assert ok, bad
-    top = st.topk("gpu")
+        ref_s = oracle.power(xs, w.bank.taps, w.bank.tap_len, rows=rows)
+        th.add(rows, out[r0:r0 + 17].cpu().numpy(), ref, ref_s)
+        _say(f"  rows {r0}..{r0 + 16}: total so far {th.total.norm_err:.3e}, own {th.own.norm_err:.3e}")
+    th.check(prec, "full plane ")
+    top = th.total.topk("gpu")
     for c in w.chirps:
         assert any(abs(i - c.r0) < 300 and abs(w.bank.z[t] + c.z0) <= 1.5 for t, i, _ in top), c
     plan.close()
