@@ -59,3 +59,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_measured_valu_issue_tracks_kernel_source(monkeypatch, tmp_path):
+    f = tmp_path / "sq.md"
+    f.write_text(f"kernel_source_sha: {bench.kernel_source_hash()}\n\nvalu_issue_per_cu_cycle: 0.93\n")
+    monkeypatch.setattr(bench, "SQ_COUNTER_FILES", {2048: str(f)})
+    assert bench.measured_valu_issue(2048) == 0.93
+    assert bench.measured_valu_issue(1024) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_valu_issue(2048) is None
+
+
+def test_unpacked_fp32_peak_from_unit_counts():
+    # one wave64 FMA instruction per CU per cycle: 256 CUs x 64 lanes x 2 x 2.4 GHz
+    assert abs(256 * 64 * 2 * 2.4e9 / 1e12 - bench.FP32_UNPACKED_PEAK_TFLOPS) < 0.1
+    assert abs(2 * bench.FP32_UNPACKED_PEAK_TFLOPS - bench.FP32_VECTOR_PEAK_TFLOPS) < 0.2
