@@ -159,10 +159,17 @@ class GpuExecutor:
     """Batched calls on `slots` streams, with one resident plan per bank."""
 
     def __init__(self, banks: dict, input_len: int, topk: int = 16, slots: int = 2,
-                 seg_fft: dict | None = None, device: str = "cuda:0", precision: str = "fp32"):
+                 seg_fft: dict | None = None, device: str = "cuda:0", precision: str = "fp32",
+                 timeline: bool = False):
         import torch
         from . import fdas
         self.torch = torch
+        # timeline: record timing events around every batch on its stream, so
+        # the device-side interval each batch was in flight can be read back
+        # (intervals()); off by default (events with timing cost a little)
+        self.timeline = bool(timeline)
+        self.spans = []
+        self.origin = None
         self.fdas = fdas
         self.topk = int(topk)
         self.slots = int(slots)
@@ -223,7 +230,14 @@ class GpuExecutor:
         plan = self.plans[bank]
         need = plan.batched_workspace_bytes([j.n for j in jobs], self.topk)
         st.wait_stream(torch.cuda.current_stream(self.device))
+        if self.timeline and self.origin is None:
+            self.origin = torch.cuda.Event(enable_timing=True)
+            self.origin.record(torch.cuda.current_stream(self.device))
+            st.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(st):
+            if self.timeline:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(st)
             # allocated on the slot's own stream: a replaced buffer is only
             # reused in that stream's order
             if self.ws[sid] is None or self.ws[sid].numel() < need:
@@ -234,9 +248,18 @@ class GpuExecutor:
             out = self.outs[sid][:len(jobs)]
             plan.convolve_batched([j.x for j in jobs], topk=self.topk, out=out, workspace=self.ws[sid])
             res = out.clone()
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=self.timeline)
             ev.record(st)
+            if self.timeline:
+                self.spans.append((ev0, ev, [j.job_id for j in jobs]))
         return (sid, ev, res, jobs)
+
+    def intervals(self):
+        """(start_ms, end_ms, job ids) of every batch on the device timeline,
+        relative to the first batch's launch (timeline=True; call after the
+        device is synchronised): start is when the batch's stream reached it,
+        end when its results were copied out."""
+        return [(self.origin.elapsed_time(a), self.origin.elapsed_time(b), ids) for a, b, ids in self.spans]
 
     def poll(self, token):
         return token[1].query()

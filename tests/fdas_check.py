@@ -9,8 +9,6 @@ import numpy as np
 
 FP32_TOL = 1e-4      # max |P_gpu - P_ref| / max P_ref for the float32 path
 MIXED_TOL = 2e-3     # the same for the 16-bit plans (FP16 storage)
-BF16_BOUND = 2e-2    # BF16 storage (8 significant bits) misses 2e-3; a regression
-                     # guard at twice the worst error measured over the test cases
 TOPK = 16
 
 
@@ -133,3 +131,69 @@ def check_against_plane(t, b, p, ref_plane, k, tol=FP32_TOL):
         assert ref_plane[c] >= kth - tol * maxref, ("extra", c)
     for c in ws - gs:
         assert ref_plane[c] <= kth + tol * maxref, ("missing", c)
+
+
+class OracleTopk:
+    """The FP64 oracle's top-k cells of one array's whole power plane,
+    computed in blocks of rows so that no plane is held whole: the k largest
+    cells by (P desc, t asc, i asc), the plane's maximum, and every cell tied
+    with or above the running k-th value (so the k-th value is exact)."""
+
+    def __init__(self, x, taps, tap_len, k: int = TOPK, rows_per_block: int = 8, nthreads: int = 0):
+        import oracle
+        self.k = k
+        m = taps.shape[0]
+        cand = []                    # (P, t, i) of every cell that may still be in the top k
+        thr = -np.inf
+        self.maxref = 0.0
+        self.n = int(np.asarray(x).shape[0])
+        for r0 in range(0, m, rows_per_block):
+            rows = list(range(r0, min(m, r0 + rows_per_block)))
+            blk = oracle.power(x, taps, tap_len, rows=rows, nthreads=nthreads)
+            self.maxref = max(self.maxref, float(blk.max()) if blk.size else 0.0)
+            flat = blk.reshape(-1)
+            if len(cand) < k:           # fewer than k cells so far: this block's k largest
+                take = min(k, flat.size)
+                sel = np.flatnonzero(flat >= np.partition(flat, flat.size - take)[flat.size - take])
+            else:
+                sel = np.flatnonzero(flat >= thr)
+            n = blk.shape[1]
+            for c in sel.tolist():
+                cand.append((float(flat[c]), rows[c // n], c % n))
+            cand.sort(key=lambda e: (-e[0], e[1], e[2]))
+            if len(cand) >= k:
+                thr = cand[k - 1][0]
+                cand = [e for e in cand if e[0] >= thr]
+        self.top = [(t, i, p) for p, t, i in cand[:k]]
+        self.kth = self.top[-1][2] if self.top else 0.0
+        # every cell at or above the k-th value (ties included)
+        self.above = {(t, i): p for p, t, i in cand}
+
+    def check(self, x, taps, tap_len, t, b, p, tol=FP32_TOL):
+        """GPU top-k list (t, b, p arrays) of this array against the oracle's,
+        with the near-tie rule: each reported power equals the oracle's power
+        at that cell within tol * max P; the list is ordered; and the cell
+        sets agree except for cells within tol * max P of the k-th value."""
+        import oracle
+        k = self.k
+        cells = taps.shape[0] * self.n
+        got = [(int(t[r]), int(b[r]), float(p[r])) for r in range(min(k, cells))]
+        if cells < k:
+            assert np.all(t[cells:] == -1) and np.all(b[cells:] == -1) and np.all(p[cells:] == -1.0)
+        slack = tol * self.maxref
+        for tt, bb, _ in got:
+            assert 0 <= tt < taps.shape[0] and 0 <= bb < self.n, (tt, bb)
+        ref_at = oracle.power_at(x, taps, tap_len, [g[0] for g in got], [g[1] for g in got])
+        for (tt, bb, pp), rv in zip(got, ref_at):
+            assert abs(pp - rv) <= slack + 1e-30, ("power", tt, bb, pp, rv)
+        for r in range(len(got) - 1):
+            a_, c_ = got[r], got[r + 1]
+            assert a_[2] > c_[2] or (a_[2] == c_[2] and (a_[0], a_[1]) < (c_[0], c_[1])), ("order", r)
+        gs = {(a_, b_): rv for (a_, b_, _), rv in zip(got, ref_at)}
+        ws = {(a_, b_) for a_, b_, _ in self.top}
+        for c, rv in gs.items():
+            if c not in ws:
+                assert rv >= self.kth - slack, ("extra", c, rv, self.kth)
+        for c in ws - set(gs):
+            assert self.above[c] <= self.kth + slack, ("missing", c, self.above[c], self.kth)
+        return max((abs(pp - rv) for (_, _, pp), rv in zip(got, ref_at)), default=0.0) / max(self.maxref, 1e-300)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from fdas_check import FP32_TOL, check_against_plane
+from fdas_check import FP32_TOL, MIXED_TOL, OracleTopk, check_against_plane
 from paper_1805_12280_amd import datagen
 
 pytestmark = pytest.mark.gpu
@@ -71,6 +71,44 @@ def test_chirps_found_in_batch(env):
         for c in batch.chirps[a]:
             assert any(abs(int(bb) - c.r0) < 300 and abs(bank.z[int(tt)] + c.z0) <= 1.5
                        for tt, bb in zip(t[a], b[a])), (a, c)
+
+
+@pytest.fixture(scope="module")
+def dm_batch():
+    """The 64-array DM-trial batch (2^19..2^22 points, 85 templates) and the
+    FP64 oracle's top-16 of every array's whole power plane (about 6e11
+    complex MACs on the host's cores, the planes never held whole)."""
+    import time
+    batch = datagen.dm_trial_batch()
+    t0 = time.perf_counter()
+    refs = []
+    for a, x in enumerate(batch.xs):
+        refs.append(OracleTopk(x, batch.bank.taps, batch.bank.tap_len, k=16, rows_per_block=17))
+        if a % 8 == 7:
+            _say(f"[oracle top-16] {a + 1} of {len(batch.xs)} arrays, {time.perf_counter() - t0:.0f} s")
+    return batch, refs
+
+
+@pytest.mark.parametrize("prec,L", [("fp32", 1024), ("fp32", 2048), ("fp16", 2048)])
+def test_full_batch_against_oracle_topk(env, dm_batch, prec, L):
+    """Every array of the full DM-trial batch: the batched call's top-16
+    against the top-16 of the FP64 oracle's whole plane of that array, on
+    the original complex64 spectra (near-tie rule at the path's bar: 1e-4 of
+    the array's peak power for float32, 2e-3 for the FP16 plan)."""
+    torch, fdas = env
+    batch, refs = dm_batch
+    bank = batch.bank
+    tol = FP32_TOL if prec == "fp32" else MIXED_TOL
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=1 << 22, seg_fft=L, precision=prec)
+    dev = [torch.from_numpy(v).cuda() for v in batch.xs]
+    if prec != "fp32":
+        dev = [torch.view_as_real(v).to(plan.input_dtype()).contiguous() for v in dev]
+    t, b, p = cands_np(fdas, plan.convolve_batched(dev, topk=16))
+    worst = 0.0
+    for a, x in enumerate(batch.xs):
+        worst = max(worst, refs[a].check(x, bank.taps, bank.tap_len, t[a], b[a], p[a], tol=tol))
+    _say(f"[full batch vs oracle] {prec} L={L}: 64 arrays ok, worst reported-power error / peak {worst:.2e}")
+    plan.close()
 
 
 @pytest.mark.parametrize("L", [1024, 2048, 4096])
