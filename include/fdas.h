@@ -238,6 +238,32 @@ int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_in, const 
                           size_t workspace_bytes, void *hip_stream);
 
 /*
+ * fdas_convolve_batched_static -- fdas_convolve_batched without a caller
+ * workspace and without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture that may not allocate, tight
+ * serving loops, harnesses that forbid hipMalloc.
+ *
+ * The workspace is a fixed array inside the library,
+ * FDAS_STATIC_WORKSPACE_BYTES on every GPU the library runs on, held from
+ * the library's first use on that GPU until the process ends; its address
+ * is looked up when a plan is created on that GPU.  The call allocates
+ * nothing (no hipMalloc, no hipFree, no allocating library routine).
+ * Arguments, output, ordering and errors are those of fdas_convolve_batched
+ * without d_workspace and workspace_bytes; a batch whose workspace
+ * (fdas_batched_workspace_bytes) exceeds FDAS_STATIC_WORKSPACE_BYTES returns
+ * FDAS_EINVAL and enqueues nothing.  A float32 plan's batch of 64 spectra of
+ * up to 2^22 points needs well under 1 MB; a 16-bit plan also stages 16 KB
+ * per segment, about 2000 segments (3.8 M points at L = 2048) in all.
+ * Every call on one GPU shares that GPU's array, and no call needs it
+ * cleared or leaves state in it that a later call reads: calls that overlap
+ * on one GPU (different streams, or a graph replay beside another call) race
+ * on the array and give wrong candidates; the caller orders them.
+ */
+#define FDAS_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+int fdas_convolve_batched_static(const fdas_plan *plan, const void *const *d_in, const int64_t *n,
+                                 int32_t count, int32_t topk, fdas_cand *d_out, void *hip_stream);
+
+/*
  * fdas_segment_fft -- the plan's L-point segment transform on its own,
  * in natural order, for `count` independent transforms (the FFT engine role
  * of Section 4.2).

@@ -78,6 +78,8 @@ struct fdas_plan {
     c32 *d_taps = nullptr;     // [M][kp], zero beyond tap_len
     int *d_tap_len = nullptr;  // [M]
     int64_t resident_bytes = 0;
+    void *static_ws = nullptr;        // this device's static workspace (fdas_convolve_batched_static)
+    hipError_t static_ws_err = hipSuccess;
 };
 
 namespace {
@@ -220,6 +222,10 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     if (e == hipSuccess) e = fdas::launch_tspec(p->d_taps, p->d_tap_len, kp, M, L, p->d_H, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "building template spectra"); }
+
+    // set-up of the static workspace on this device (looked up once per
+    // device; a failure is reported by the calls that need it)
+    p->static_ws_err = fdas::static_workspace(p->device, &p->static_ws);
 
     p->fused_per_cu = fdas::fused_blocks_per_cu(L);
     p->g.topk_fit = fdas::topk_blocks_per_cu(L);
@@ -435,6 +441,22 @@ FDAS_API int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_i
     if (rc == FDAS_OK) rc = fdas::check_workspace(sh, d_workspace, workspace_bytes);
     if (rc != FDAS_OK) return rc;
     return launch_batched(plan, d_in, sh, topk, d_out, d_workspace, (hipStream_t)hip_stream);
+}
+
+FDAS_API int fdas_convolve_batched_static(const fdas_plan *plan, const void *const *d_in, const int64_t *n,
+                                          int32_t count, int32_t topk, fdas_cand *d_out, void *hip_stream)
+{
+    fdas::last_error().clear();
+    if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    fdas::BatchShape sh;
+    int rc = fdas::batch_shape(plan->g, n, count, topk, sh);
+    if (rc == FDAS_OK) rc = fdas::check_batched_ptrs(plan->g, d_in, count, d_out);
+    if (rc == FDAS_OK) rc = fdas::check_static_workspace(sh);
+    if (rc != FDAS_OK) return rc;
+    if (plan->static_ws_err != hipSuccess || !plan->static_ws)
+        return hip_fail(plan->static_ws_err != hipSuccess ? plan->static_ws_err : hipErrorInvalidSymbol,
+                        "looking up the static workspace");
+    return launch_batched(plan, d_in, sh, topk, d_out, plan->static_ws, (hipStream_t)hip_stream);
 }
 
 FDAS_API int fdas_segment_fft(const fdas_plan *plan, const void *d_in, void *d_out, int64_t count,

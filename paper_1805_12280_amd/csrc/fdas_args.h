@@ -213,4 +213,14 @@ inline int check_workspace(const BatchShape &sh, const void *d_workspace, size_t
     return FDAS_OK;
 }
 
+// A batch for fdas_convolve_batched_static: its workspace must fit the
+// library's static array.
+inline int check_static_workspace(const BatchShape &sh)
+{
+    if (sh.bytes > FDAS_STATIC_WORKSPACE_BYTES)
+        return fail(FDAS_EINVAL, "batch needs %zu bytes of workspace; the static workspace holds %zu", sh.bytes,
+                    (size_t)FDAS_STATIC_WORKSPACE_BYTES);
+    return FDAS_OK;
+}
+
 }  // namespace fdas

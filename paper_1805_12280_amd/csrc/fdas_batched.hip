@@ -12,10 +12,43 @@
 //
 // Order of cells (Cand, beats in fdas_internal.h): power descending, then
 // template ascending, then bin ascending.
+#include <mutex>
+
 #include "fdas_internal.h"
 #include "seg_fft.h"
 
 namespace fdas {
+
+// Workspace of fdas_convolve_batched_static: a fixed device array, one per
+// GPU the library runs on, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel or a copy (on the host it names a
+// stand-in, not device memory): it uses the device address that
+// static_workspace() looked up on that device.
+static __device__ __align__(256) unsigned char scratch[FDAS_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+bool g_scratch_done[kMaxDevices];
+}  // namespace
+
+hipError_t static_workspace(int device, void **ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        // once per device, with that device current (the caller's contract)
+        void *p = nullptr;
+        g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_addr[device] = g_scratch_err[device] == hipSuccess ? p : nullptr;
+        g_scratch_done[device] = true;
+    }
+    *ptr = g_scratch_addr[device];
+    return g_scratch_err[device];
+}
 
 // Work item u in [0, items) of the batch is (array a, segment s, template t),
 // ordered by array, then segment, then template; bs.item_begin[a] is the

@@ -128,5 +128,8 @@ struct MixedTopkArgs {
 int mixed_topk_blocks_per_cu(bool bf);
 hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st);
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
+// Device address of the static workspace on `device` (which must be the
+// current device); looked up once per device, the same result after that.
+hipError_t static_workspace(int device, void **ptr);
 
 }  // namespace fdas

@@ -23,10 +23,11 @@ PRECISIONS = {"fp32": FDAS_FP32, "fp16": FDAS_FP16, "bf16": FDAS_BF16}
 
 MAX_BATCH = 128
 MAX_TOPK = 32
+STATIC_WORKSPACE_BYTES = 32 << 20
 
 EXPORTED = ("fdas_plan_create", "fdas_plan_set_workgroups_per_cu", "fdas_convolve", "fdas_tdfir",
             "fdas_batched_workspace_bytes",
-            "fdas_convolve_batched", "fdas_segment_fft",
+            "fdas_convolve_batched", "fdas_convolve_batched_static", "fdas_segment_fft",
             "fdas_plan_template_spectra", "fdas_plan_info", "fdas_plan_destroy",
             "fdas_strerror", "fdas_last_error", "fdas_variant_name")
 
@@ -73,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     lib.fdas_batched_workspace_bytes.restype = ctypes.c_int
     lib.fdas_convolve_batched.argtypes = [vp, vp, vp, i32, i32, vp, vp, ctypes.c_size_t, vp]
     lib.fdas_convolve_batched.restype = ctypes.c_int
+    lib.fdas_convolve_batched_static.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+    lib.fdas_convolve_batched_static.restype = ctypes.c_int
     lib.fdas_segment_fft.argtypes = [vp, vp, vp, i64, i32, vp]
     lib.fdas_segment_fft.restype = ctypes.c_int
     lib.fdas_plan_template_spectra.argtypes = [vp, vp]
@@ -287,6 +290,26 @@ class Plan:
         ns = (ctypes.c_int64 * count)(*lengths)
         check(self._lib.fdas_convolve_batched(self._h, ptrs, ns, count, int(topk), _ptr(out),
                                               _ptr(workspace), workspace.numel(), _stream_handle(stream)))
+        return out
+
+    def convolve_batched_static(self, xs, topk: int = 16, out=None, stream=None):
+        """convolve_batched with the library's static workspace: the call
+        allocates no device memory (pass `out` to allocate none here either).
+        Calls that overlap on one GPU race on that workspace."""
+        import torch
+        xs = list(xs)
+        count = len(xs)
+        if count < 1 or count > MAX_BATCH:
+            raise FdasError(FDAS_EINVAL, f"batch of {count} arrays; 1..{MAX_BATCH} supported")
+        if out is None:
+            with _on_stream(stream):
+                out = torch.empty((count, topk, 3), dtype=torch.int32, device=xs[0].device)
+        if out.dtype != torch.int32 or tuple(out.shape) != (count, topk, 3) or not out.is_contiguous():
+            raise FdasError(FDAS_EINVAL, "out must be a contiguous int32 [count, topk, 3] tensor")
+        ptrs = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+        ns = (ctypes.c_int64 * count)(*[int(x.shape[0]) for x in xs])
+        check(self._lib.fdas_convolve_batched_static(self._h, ptrs, ns, count, int(topk), _ptr(out),
+                                                     _stream_handle(stream)))
         return out
 
     def segment_fft(self, x, direction: int = -1, stream=None):

@@ -207,6 +207,25 @@ static void batch_args()
         }
         CHECK(fdas::check_workspace(s, ws, s.bytes) == FDAS_OK);
         CHECK(fdas::check_workspace(s, ws, s.bytes - 1) == FDAS_EINVAL);
+        CHECK(fdas::check_static_workspace(s) == (s.bytes <= FDAS_STATIC_WORKSPACE_BYTES ? FDAS_OK : FDAS_EINVAL));
+    }
+    // the static workspace: a float32 DM-trial batch fits, a 16-bit batch of
+    // 2^22 points (2185 staged segments of 16 KB) does not
+    {
+        PlanGeom h;
+        CHECK(fdas::check_plan_args(&dummy, 85, 101, int64_t(1) << 22, 2048, 0, h) == FDAS_OK);
+        h.num_cu = 256;
+        h.topk_fit = 2;
+        std::vector<int64_t> big(64, int64_t(1) << 22);
+        fdas::BatchShape s;
+        CHECK(fdas::batch_shape(h, big.data(), 64, 16, s) == FDAS_OK);
+        CHECK(s.bytes < (size_t(1) << 20) && fdas::check_static_workspace(s) == FDAS_OK);
+        CHECK(fdas::check_plan_args(&dummy, 85, 101, int64_t(1) << 22, 2048, FDAS_FP16, h) == FDAS_OK);
+        CHECK(fdas::batch_shape(h, big.data(), 1, 16, s) == FDAS_OK);
+        CHECK(fdas::check_static_workspace(s) == FDAS_EINVAL);
+        std::vector<int64_t> small(2, 1 << 20);
+        CHECK(fdas::batch_shape(h, small.data(), 2, 16, s) == FDAS_OK);
+        CHECK(fdas::check_static_workspace(s) == FDAS_OK);
     }
 }
 
