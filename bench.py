@@ -23,6 +23,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -33,13 +35,16 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector: 256 CU x 6
 # most one wave64 VALU instruction per CU per cycle, i.e. 256 CU x 64 lanes x
 # 2 (FMA) x 2.4 GHz.
 FP32_UNPACKED_PEAK_TFLOPS = 78.6
+FP16_MFMA_PEAK_TFLOPS = 2500.0        # MI355X published dense binary16 matrix-core peak
 SQ_COUNTER_FILES = {L: os.path.join(ROOT, "profiles", f"fdfir_fused_ska-85x2^22_L{L}_sq_counters.md")
                     for L in (1024, 2048)}
 SUSTAINED_S = 1.5                     # back-to-back calls timed for the sustained rate
 KERNEL_SOURCES = ("paper_1805_12280_amd/csrc/seg_fft.h", "paper_1805_12280_amd/csrc/fdas_internal.h",
-                  "paper_1805_12280_amd/csrc/fdas_kernels.hip")
-TRAFFIC_FILES = {L: os.path.join(ROOT, "profiles", f"fdfir_fused_ska-85x2^22_L{L}_traffic.md")
-                 for L in (1024, 2048, 4096)}
+                  "paper_1805_12280_amd/csrc/fdas_kernels.hip", "paper_1805_12280_amd/csrc/fdas_direct.hip")
+# HBM traffic summaries of one fdas_convolve call, keyed by (segment length,
+# direct templates): the call's launches summed
+TRAFFIC_FILES = {(L, md): os.path.join(ROOT, "profiles", f"fdas_convolve_ska-85x2^22_L{L}_direct{md}_traffic.md")
+                 for L in (1024, 2048, 4096) for md in range(0, 86, 8)}
 
 
 def log(*a):
@@ -54,15 +59,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(L):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary for this
-    segment length, if it was taken on the current kernel source; else None."""
-    path = TRAFFIC_FILES.get(L)
+def measured_traffic(L, md=0):
+    """HBM bytes per fdas_convolve call from the committed rocprofv3 PMC
+    summary for this segment length and direct split, if it was taken on the
+    current kernel source; else None."""
+    path = TRAFFIC_FILES.get((L, md))
     if path is None or not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
-    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_bytes = re.search(r"traffic_bytes_per_call:\s*([0-9.eE+]+)", text)
     if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_bytes.group(1))
@@ -235,6 +241,55 @@ def cpu_baseline_leg(w, P_gpu_rows_fn, target_s: float):
     }, {"rows": m, "outputs": n_s, "norm_err": st.norm_err, "rrmse": st.rrmse}
 
 
+def direct_mfma_flops(n, tap_len, md):
+    """Matrix-core operations the direct launch issues for the md shortest
+    templates: per 16 outputs and block of 8 templates, 3 binary16 products
+    (high x high, high x low, low x high) of 16 x 16 x 32 per 16 taps of the
+    block's longest template."""
+    lens = np.sort(np.asarray(tap_len))[:md]
+    tiles = math.ceil(n / 16)
+    ops = 0
+    for b in range(0, md, 8):
+        nk = max(1, math.ceil(int(lens[b:b + 8].max()) / 16))
+        ops += tiles * 3 * nk * 2 * 16 * 16 * 32
+    return ops
+
+
+def split_legs(torch, fdas, w, x, L, md, steps, warmup):
+    """Each launch of a split call timed on its own: the md shortest
+    templates on a plan that runs them all directly, the rest on an
+    overlap-save plan (same segment length), each writing its rows of a
+    plane.  Their sum is close to the split call's time."""
+    m, n = w.bank.num_templates, w.n
+    if md == 0:
+        return {"direct": None, "overlap_save": None}
+    order = np.argsort(w.bank.tap_len, kind="stable")
+    res = {}
+    for name, idx in (("direct", order[:md]), ("overlap_save", order[md:])):
+        if len(idx) == 0:
+            res[name] = None
+            continue
+        p = fdas.Plan(np.ascontiguousarray(w.bank.taps[idx]), np.ascontiguousarray(w.bank.tap_len[idx]),
+                      input_len=n, seg_fft=L)
+        p.set_direct_templates(len(idx) if name == "direct" else 0)
+        o = torch.empty((len(idx), n), dtype=torch.float32, device=x.device)
+        t = time_calls(torch, lambda: p.convolve(x, out=o), steps, warmup)
+        by = 8 * n + 4 * len(idx) * n
+        ent = {"templates": len(idx), "ms": t, "hbm_gbs": by / (t * 1e-3) / 1e9,
+               "hbm_frac": by / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if name == "direct":
+            fl = direct_mfma_flops(n, w.bank.tap_len, len(idx))
+            ent.update({"mfma_tflops": fl / (t * 1e-3) / 1e12, "mfma_peak_tflops": FP16_MFMA_PEAK_TFLOPS,
+                        "mfma_frac": fl / (t * 1e-3) / 1e12 / FP16_MFMA_PEAK_TFLOPS})
+        else:
+            fl = nominal_flops(n, len(idx), L, w.bank.k_max)
+            ent.update({"tflops": fl / (t * 1e-3) / 1e12, "peak_tflops": FP32_UNPACKED_PEAK_TFLOPS,
+                        "frac": fl / (t * 1e-3) / 1e12 / FP32_UNPACKED_PEAK_TFLOPS})
+        res[name] = ent
+        p.close()
+    return res
+
+
 def batched_leg(torch, fdas, steps, warmup):
     """64 DM-trial spectra (2^19..2^22 points) x 85 templates per step, top-16
     cells per array, the segment length picked by the autotuner, the call
@@ -244,7 +299,7 @@ def batched_leg(torch, fdas, steps, warmup):
     batch = datagen.dm_trial_batch()
     bank = batch.bank
     dev = [torch.from_numpy(x).to("cuda:0") for x in batch.xs]
-    best, wg, tuned = autotune.tune(bank, dev, mode="batched", topk=16, use_cache=False)
+    best, wg, _, tuned = autotune.tune(bank, dev, mode="batched", topk=16, use_cache=False)
     log(f"autotune (ms per batch, L/workgroups per CU): {tuned} -> L = {best}, wg = {wg}")
     plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(batch.lengths), seg_fft=best)
     plan.set_workgroups_per_cu(wg)
@@ -490,11 +545,13 @@ def main():
         L = args.seg_fft
     else:
         from paper_1805_12280_amd import autotune
-        L, wg, tuned = autotune.tune(w.bank, [x], mode="plane", use_cache=False)
-        log(f"autotune (ms per call, L/workgroups per CU, 0 = full grid): {tuned} -> L = {L}, wg = {wg}")
+        L, wg, direct, tuned = autotune.tune(w.bank, [x], mode="plane", use_cache=False)
+        log(f"autotune (ms per call, L/workgroups per CU/direct templates, 0 = full grid): {tuned} -> "
+            f"L = {L}, wg = {wg}, direct = {direct}")
     plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=L)
     if not args.seg_fft:
         plan.set_workgroups_per_cu(wg)
+        plan.set_direct_templates(direct)
     out = torch.empty((m, n), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log(f"plan: {plan.info.as_dict()} variant={plan.variant}")
@@ -503,9 +560,12 @@ def main():
     value = m * n / (ms * 1e-3)
     abytes = algorithmic_bytes(n, m, L)
     achieved = abytes / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(L)
+    traffic = measured_traffic(L, plan.info.direct_templates)
     tflops = nominal_flops(n, m, L, k_max) / (ms * 1e-3) / 1e12
     log(f"fdas_convolve: {ms:.4f} ms/step, {value:.4e} template-samples/s, {achieved:.1f} GB/s")
+    md = plan.info.direct_templates
+    kernels = split_legs(torch, fdas, w, x, L, md, args.steps, args.warmup)
+    log(f"launches: {kernels}")
 
     result = {
         "metric": METRIC,
@@ -523,20 +583,26 @@ def main():
                 "85 chirp templates z=-42..42)",
         "config": {"workload": w.name, "templates": m, "n": n, "k_max": k_max,
                    "taps_total": int(w.bank.tap_len.sum()), "seg_fft": L,
-                   "workgroups_per_cu": plan.info.wg_per_cu, "autotune_ms": tuned,
-                   "path": "overlap-save FDFIR + |y|^2, one fused launch"},
+                   "workgroups_per_cu": plan.info.wg_per_cu, "direct_templates": md,
+                   "autotune_ms": tuned,
+                   "path": ("direct convolution of the %d shortest templates on the matrix cores + "
+                            "overlap-save FDFIR of the other %d, |y|^2 in both launches" % (md, m - md)
+                            if md else "overlap-save FDFIR + |y|^2, one fused launch")},
         # the metric's roofline: algorithmic bytes per launch (input once,
         # plane once, template spectra once) over the launch's mean duration
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": abytes},
-        # the same launches priced as arithmetic: nominal FFT operations against
-        # the FP32 FMA peak this build can issue (no packed FP32), with the
-        # VALU issue rate read from the committed SQ counters
+        # the overlap-save launch priced as arithmetic: nominal FFT operations
+        # of all templates against the FP32 FMA peak this build can issue (no
+        # packed FP32), with the VALU issue rate read from the committed SQ
+        # counters; with a direct split, the per-launch figures are in
+        # "launches"
         "alu_roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_UNPACKED_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": tflops / FP32_UNPACKED_PEAK_TFLOPS,
                          "published_fp32_vector_peak": FP32_VECTOR_PEAK_TFLOPS,
                          "valu_issue_per_cu_cycle": measured_valu_issue(L)},
+        "launches": kernels,
         "step_ms": percentiles(per_step),
     }
     sus = sustained(torch, lambda: plan.convolve(x, out=out), ms)

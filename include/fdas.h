@@ -75,6 +75,7 @@ typedef struct {
     int32_t device;           /* HIP device ordinal the plan lives on */
     int32_t wg_per_cu_max;    /* persistent workgroups per CU that fit (fused launch) */
     int32_t wg_per_cu;        /* the cap in force (fdas_plan_set_workgroups_per_cu), 0 = none */
+    int32_t direct_templates; /* templates fdas_convolve runs by direct convolution (float32 plans) */
 } fdas_plan_info_t;
 
 /*
@@ -143,8 +144,32 @@ int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *tap_len,
 int fdas_plan_set_workgroups_per_cu(fdas_plan *plan, int32_t per_cu);
 
 /*
+ * fdas_plan_set_direct_templates -- how a float32 plan splits its bank.
+ *
+ * fdas_convolve runs a template either by overlap-save (Alg. 2; the cost per
+ * output is one inverse FFT of L points whatever the tap count) or by direct
+ * convolution (Eq. (1); the cost grows with the tap count), the two routes
+ * the paper compares.  The plan orders its templates by tap count and runs
+ * the shortest ones by direct convolution on the matrix cores (binary16 high
+ * and low parts of every operand, three products, float32 accumulation: the
+ * same float32-class result), in blocks of 8, and the rest by overlap-save.
+ * m = number of shortest templates to run directly, rounded down to a
+ * multiple of 8 (m >= M: all of them); blocks whose longest template has
+ * more than 96 taps always run by overlap-save.  m = 0 runs the whole bank
+ * by overlap-save; m = -1 restores the plan's default, the blocks for which
+ * a cost model of the two kernels favours the direct form.
+ * fdas_plan_info reports the split in force.  Not to be called while calls
+ * on the plan may be enqueued from other host threads.
+ * Errors: FDAS_EINVAL (NULL plan, m < -1), FDAS_EUNSUPPORTED (16-bit plan).
+ */
+int fdas_plan_set_direct_templates(fdas_plan *plan, int32_t m);
+
+/*
  * fdas_convolve -- the overlap-save FDFIR hot path (Alg. 2 with the power
- * of Section 4.3), one launch for all M templates.
+ * of Section 4.3) for all M templates.  A float32 plan runs its shortest
+ * templates by direct convolution on the matrix cores (one launch, see
+ * fdas_plan_set_direct_templates) and the rest by overlap-save (one fused
+ * launch); both write their rows of the same plane, in stream order.
  *
  *   plan       from fdas_plan_create (not NULL).
  *   d_in       device complex64 [n], 8-byte aligned; for a mixed plan, pairs

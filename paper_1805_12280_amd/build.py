@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfdas.so")
-SOURCES = ["fdas_kernels.hip", "fdas_batched.hip", "fdas_mixed.hip", "fdas_abi.cpp"]
+SOURCES = ["fdas_kernels.hip", "fdas_batched.hip", "fdas_mixed.hip", "fdas_direct.hip", "fdas_abi.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions stay off in every device compile.

@@ -80,6 +80,16 @@ struct fdas_plan {
     int64_t resident_bytes = 0;
     void *static_ws = nullptr;        // this device's static workspace (fdas_convolve_batched_static)
     hipError_t static_ws_err = hipSuccess;
+    // float32 plans: the bank's rows in order of tap count; the first
+    // DIRECT_BLOCK * direct_blocks of them run on the matrix cores (direct
+    // convolution), the rest by overlap-save
+    std::vector<int> order;
+    int *d_order = nullptr;           // [M]
+    c32 *d_Hs = nullptr;              // [M][L]: d_H's rows in that order (the overlap-save launch)
+    fdas::DirectTables dt;            // the leading blocks of 8 that direct convolution can take
+    void *d_dA = nullptr;
+    int *d_dmeta = nullptr;           // aoff [nblk], nks [nblk], rows [8 nblk], pexp [8 nblk]
+    int direct_blocks = 0;            // blocks in use
 };
 
 namespace {
@@ -95,6 +105,10 @@ void free_plan(fdas_plan *p)
     if (p->d_mat) (void)hipFree(p->d_mat);
     if (p->d_stage) (void)hipFree(p->d_stage);
     if (p->stage_free) (void)hipEventDestroy(p->stage_free);
+    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_Hs) (void)hipFree(p->d_Hs);
+    if (p->d_dA) (void)hipFree(p->d_dA);
+    if (p->d_dmeta) (void)hipFree(p->d_dmeta);
     for (const StreamMark &m : p->marks) (void)hipEventDestroy(m.done);
     delete p;
 }
@@ -128,6 +142,29 @@ hipError_t mark_use(const fdas_plan *p, hipStream_t st)
     }
     return hipEventRecord(slot->done, st);
 }
+
+// Default split of a float32 plan: the leading blocks of DIRECT_BLOCK
+// templates (in order of tap count) run on the matrix cores while the
+// block's direct cost stays below overlap-save's for its rows.  Per 16
+// outputs and SIMD, a block of NK steps of 16 taps issues 3 NK binary16
+// products of 16 cycles; overlap-save costs about 39 cycles per template
+// and 16 outputs (36 VALU instructions per point at 4 cycles per wave64
+// instruction and ~93% issue).  Taking the products at 80% of their issue
+// rate, a full block goes direct up to NK = 5 (80 taps), the crossover
+// measured on the 85-template bank; a short last block only while its few
+// rows still pay for the block's products.
+int default_direct_blocks(const fdas_plan *p)
+{
+    int nb = 0;
+    for (int b = 0; b < p->dt.nblk; ++b) {
+        const int rows = std::min(fdas::DIRECT_BLOCK, p->g.M - fdas::DIRECT_BLOCK * b);
+        if (3 * p->dt.nks[b] * 16 > 39 * rows * 4 / 5) break;
+        nb = b + 1;
+    }
+    return nb;
+}
+
+int direct_templates(const fdas_plan *p) { return std::min(p->g.M, fdas::DIRECT_BLOCK * p->direct_blocks); }
 
 int64_t fused_grid(const fdas_plan *p, int64_t items)
 {
@@ -227,6 +264,51 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
     // device; a failure is reported by the calls that need it)
     p->static_ws_err = fdas::static_workspace(p->device, &p->static_ws);
 
+    // rows by tap count, and the direct-convolution tables of the leading
+    // blocks of 8 whose longest template the matrix-core kernel takes
+    p->order.resize((size_t)M);
+    for (int t = 0; t < M; ++t) p->order[t] = t;
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) { return lens[a] < lens[b]; });
+    e = hipMalloc((void **)&p->d_order, sizeof(int) * (size_t)M);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_order, p->order.data(), sizeof(int) * (size_t)M, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "row order"); }
+    p->resident_bytes += (int64_t)(sizeof(int) * (size_t)M);
+    if (prec == 0) {
+        e = hipMalloc((void **)&p->d_Hs, bytes_H);
+        for (int t = 0; t < M && e == hipSuccess; ++t)
+            e = hipMemcpy(p->d_Hs + (size_t)t * L, p->d_H + (size_t)p->order[t] * L, sizeof(c32) * (size_t)L,
+                          hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) { free_plan(p); return hip_fail(e, "spectra in row order"); }
+        p->resident_bytes += (int64_t)bytes_H;
+    }
+    if (prec == 0) {
+        int nblk = 0;
+        constexpr int BT = fdas::DIRECT_BLOCK;
+        while (BT * nblk < M) {
+            int kmax = 0;
+            for (int tt = 0; tt < BT && BT * nblk + tt < M; ++tt) kmax = std::max(kmax, lens[p->order[BT * nblk + tt]]);
+            if (fdas::direct_nk(kmax) > fdas::DIRECT_MAX_NK) break;
+            ++nblk;
+        }
+        if (nblk > 0) {
+            fdas::build_direct_tables(h.data(), lens.data(), M, kp, p->order, nblk, p->dt);
+            std::vector<int> meta;
+            meta.insert(meta.end(), p->dt.aoff.begin(), p->dt.aoff.end());
+            meta.insert(meta.end(), p->dt.nks.begin(), p->dt.nks.end());
+            meta.insert(meta.end(), p->dt.rows.begin(), p->dt.rows.end());
+            meta.insert(meta.end(), p->dt.pexp.begin(), p->dt.pexp.end());
+            const size_t bytes_a = sizeof(uint4) * p->dt.A.size(), bytes_m = sizeof(int) * meta.size();
+            e = hipMalloc(&p->d_dA, bytes_a);
+            if (e == hipSuccess) e = hipMalloc((void **)&p->d_dmeta, bytes_m);
+            if (e == hipSuccess) e = hipMemcpy(p->d_dA, p->dt.A.data(), bytes_a, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(p->d_dmeta, meta.data(), bytes_m, hipMemcpyHostToDevice);
+            if (e != hipSuccess) { free_plan(p); return hip_fail(e, "direct-convolution tables"); }
+            p->resident_bytes += (int64_t)(bytes_a + bytes_m);
+            p->direct_blocks = default_direct_blocks(p);
+        }
+    }
+
     p->fused_per_cu = fdas::fused_blocks_per_cu(L);
     p->g.topk_fit = fdas::topk_blocks_per_cu(L);
     if (prec != 0) {
@@ -303,22 +385,47 @@ FDAS_API int fdas_convolve(const fdas_plan *plan, const void *d_in, int64_t n, f
         plan->stage_stream = st;
         return FDAS_OK;
     }
-    fdas::FusedArgs a;
-    a.x = d_in;
-    a.n = n;
-    a.H = plan->d_H;
-    a.twL = plan->d_tw;
-    a.M = g.M;
-    a.D = g.D;
-    a.V = g.V;
-    a.L = g.L;
-    a.items = g.segments(n) * g.M;
-    a.grid = fused_grid(plan, a.items);
-    a.P = d_power;
-    a.ld = ld_power;
-    hipError_t e = fdas::launch_fused(a, st);
-    if (e == hipSuccess) e = mark_use(plan, st);
-    if (e != hipSuccess) return hip_fail(e, "launching the fused FDFIR kernel");
+    // the shortest templates by direct convolution on the matrix cores, the
+    // rest by overlap-save; both write their rows of the same plane
+    const int md = direct_templates(plan), mf = g.M - md;
+    hipError_t e = hipSuccess;
+    if (md > 0) {
+        const int nb = plan->direct_blocks, nall = plan->dt.nblk;
+        fdas::DconvArgs d;
+        d.x = d_in;
+        d.n = n;
+        d.A = plan->d_dA;
+        d.aoff = plan->d_dmeta;
+        d.nks = plan->d_dmeta + nall;
+        d.rows = plan->d_dmeta + 2 * nall;
+        d.pexp = plan->d_dmeta + 2 * nall + fdas::DIRECT_BLOCK * nall;
+        d.nblk = nb;
+        d.kpmax = 16 * plan->dt.nks[nb - 1];         // blocks are in order of tap count
+        d.P = d_power;
+        d.ld = ld_power;
+        e = fdas::launch_dconv(d, st);
+        if (e != hipSuccess) return hip_fail(e, "launching the direct-convolution kernel");
+    }
+    if (mf > 0) {
+        fdas::FusedArgs a;
+        a.x = d_in;
+        a.n = n;
+        a.H = plan->d_Hs + (size_t)md * g.L;
+        a.twL = plan->d_tw;
+        a.rows = plan->d_order + md;
+        a.M = mf;
+        a.D = g.D;
+        a.V = g.V;
+        a.L = g.L;
+        a.items = g.segments(n) * mf;
+        a.grid = fused_grid(plan, a.items);
+        a.P = d_power;
+        a.ld = ld_power;
+        e = fdas::launch_fused(a, st);
+        if (e != hipSuccess) return hip_fail(e, "launching the fused FDFIR kernel");
+    }
+    e = mark_use(plan, st);
+    if (e != hipSuccess) return hip_fail(e, "recording the call's completion");
     return FDAS_OK;
 }
 
@@ -504,6 +611,22 @@ FDAS_API int fdas_plan_set_workgroups_per_cu(fdas_plan *plan, int32_t per_cu_cap
     return FDAS_OK;
 }
 
+FDAS_API int fdas_plan_set_direct_templates(fdas_plan *plan, int32_t m)
+{
+    fdas::last_error().clear();
+    if (!plan) return fail(FDAS_EINVAL, "plan is NULL");
+    if (m < -1) return fail(FDAS_EINVAL, "m=%d < -1", m);
+    if (plan->g.prec != 0) return fail(FDAS_EUNSUPPORTED, "direct convolution is built for float32 plans only");
+    if (m == -1) {
+        plan->direct_blocks = default_direct_blocks(plan);
+        return FDAS_OK;
+    }
+    constexpr int BT = fdas::DIRECT_BLOCK;
+    const int want = m >= plan->g.M ? (plan->g.M + BT - 1) / BT : m / BT;
+    plan->direct_blocks = std::min(want, plan->dt.nblk);
+    return FDAS_OK;
+}
+
 FDAS_API int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out)
 {
     fdas::last_error().clear();
@@ -523,6 +646,7 @@ FDAS_API int fdas_plan_info(const fdas_plan *plan, fdas_plan_info_t *out)
     out->device = plan->device;
     out->wg_per_cu_max = g.prec ? plan->mixed_per_cu : plan->fused_per_cu;
     out->wg_per_cu = g.wg_cap;
+    out->direct_templates = direct_templates(plan);
     return FDAS_OK;
 }
 

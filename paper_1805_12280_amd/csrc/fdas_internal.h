@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fdas_args.h"
 
 namespace fdas {
@@ -26,8 +28,9 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 struct FusedArgs {
     const void *x;        // complex64 [n]
     int64_t n;
-    const void *H;        // complex64 [M][L], permuted order
+    const void *H;        // complex64 [M][L], permuted order: the spectra of the templates run
     const c32 *twL;       // complex64 [L]
+    const int *rows;      // [M]: plane row of each template run
     int M, D, V, L;       // D: discarded points per segment, V = L - D kept
     int64_t items;        // S * M
     int64_t grid;         // workgroups
@@ -128,6 +131,35 @@ struct MixedTopkArgs {
 int mixed_topk_blocks_per_cu(bool bf);
 hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st);
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
+
+// Direct convolution on the matrix cores (fdas_direct.hip) for the plan's
+// shortest templates: blocks of DIRECT_BLOCK templates (in order of tap
+// count), each with NK <= DIRECT_MAX_NK steps of 16 taps.
+constexpr int DIRECT_BLOCK = 8;
+constexpr int DIRECT_MAX_NK = 6;
+struct DirectTables {
+    int nblk = 0;
+    int kpmax = 16;                // 16 * the largest NK of the blocks
+    std::vector<int> nks;          // [nblk]
+    std::vector<int> aoff;         // [nblk] first uint4 of each block's operands in A
+    std::vector<int> rows;         // [nblk][DIRECT_BLOCK] plane row of each template, -1 = padding
+    std::vector<int> pexp;         // [nblk][DIRECT_BLOCK] -2 x the template's scale exponent
+    std::vector<uint4> A;          // split tap operands, per block and step: 64 lanes hi, 64 lanes lo
+};
+int direct_nk(int taps);
+// order: the bank's rows by tap count; block b takes order[DIRECT_BLOCK b ..)
+void build_direct_tables(const c32 *taps, const int *tap_len, int M, int kp, const std::vector<int> &order,
+                         int nblk, DirectTables &out);
+struct DconvArgs {
+    const void *x;
+    int64_t n;
+    const void *A;
+    const int *aoff, *nks, *rows, *pexp;
+    int nblk, kpmax;
+    float *P;
+    int64_t ld;
+};
+hipError_t launch_dconv(const DconvArgs &a, hipStream_t st);
 // Device address of the static workspace on `device` (which must be the
 // current device); looked up once per device, the same result after that.
 hipError_t static_workspace(int device, void **ptr);

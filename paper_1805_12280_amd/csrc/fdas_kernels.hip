@@ -76,10 +76,13 @@ __global__ void tspec_kernel(const c32 *__restrict__ taps, const int *__restrict
 // so the spectrum X is invariant in the inner loop: with one flat loop over
 // items and the forward transform under a branch, X is a loop-carried value
 // and the compiler copies its 32 registers twice per item.
+// The kernel runs M templates of the bank: template t's spectra are H[t] and
+// its powers go to row rows[t] of the plane (the plan passes its rows routed
+// to overlap-save, with their spectra in that order).
 template <int L>
 __global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_fused_kernel(
     const c32 *__restrict__ x, int64_t n, const c32 *__restrict__ H, const c32 *__restrict__ twL,
-    int M, int D, int V, int64_t items, float *__restrict__ P, int64_t ld)
+    const int *__restrict__ rows, int M, int D, int V, int64_t items, float *__restrict__ P, int64_t ld)
 {
     using SG = Seg<L>;
     constexpr int T = SG::T;
@@ -140,6 +143,7 @@ __global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_fused_kernel(
             // next item's template spectra, in flight during this transform
             // (after the last item this reads a valid row that is never used)
             const int tn = (t + 1 == M) ? 0 : t + 1;
+            const int row = rows[t];
             {
                 const c32 *Ht = H + (int64_t)tn * L;
 #pragma unroll
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(L / 16, L == 8192 ? 1 : 2) void fdfir_fused_kernel(
             __syncthreads();
             SG::inv0(tau, v, bufA, tw0);
             const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(P + (int64_t)t * ld + s * V, 0, 4 * nkeep, kBufWord3);
+                __builtin_amdgcn_make_buffer_rsrc(P + (int64_t)row * ld + s * V, 0, 4 * nkeep, kBufWord3);
 #pragma unroll
             for (int m = 0; m < 16; ++m)
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(norm2(v[m])), rs, 4 * (tau + T * m - D), 0,
@@ -379,7 +383,7 @@ int fused_blocks_per_cu(int L)
 template <int L> static void launch_fused_t(const FusedArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL((fdfir_fused_kernel<L>), dim3((unsigned)a.grid), dim3(L / 16), 0, st,
-                       (const c32 *)a.x, a.n, (const c32 *)a.H, (const c32 *)a.twL, a.M, a.D,
+                       (const c32 *)a.x, a.n, (const c32 *)a.H, (const c32 *)a.twL, a.rows, a.M, a.D,
                        a.V, a.items, a.P, a.ld);
 }
 

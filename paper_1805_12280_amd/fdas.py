@@ -25,7 +25,8 @@ MAX_BATCH = 128
 MAX_TOPK = 32
 STATIC_WORKSPACE_BYTES = 32 << 20
 
-EXPORTED = ("fdas_plan_create", "fdas_plan_set_workgroups_per_cu", "fdas_convolve", "fdas_tdfir",
+EXPORTED = ("fdas_plan_create", "fdas_plan_set_workgroups_per_cu", "fdas_plan_set_direct_templates",
+            "fdas_convolve", "fdas_tdfir",
             "fdas_batched_workspace_bytes",
             "fdas_convolve_batched", "fdas_convolve_batched_static", "fdas_segment_fft",
             "fdas_plan_template_spectra", "fdas_plan_info", "fdas_plan_destroy",
@@ -46,7 +47,7 @@ class PlanInfo(ctypes.Structure):
                 ("resident_bytes", ctypes.c_int64), ("threads_per_fft", ctypes.c_int32),
                 ("fused_grid", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("wg_per_cu_max", ctypes.c_int32),
-                ("wg_per_cu", ctypes.c_int32)]
+                ("wg_per_cu", ctypes.c_int32), ("direct_templates", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     lib.fdas_plan_template_spectra.restype = ctypes.c_int
     lib.fdas_plan_set_workgroups_per_cu.argtypes = [vp, i32]
     lib.fdas_plan_set_workgroups_per_cu.restype = ctypes.c_int
+    lib.fdas_plan_set_direct_templates.argtypes = [vp, i32]
+    lib.fdas_plan_set_direct_templates.restype = ctypes.c_int
     lib.fdas_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.fdas_plan_info.restype = ctypes.c_int
     lib.fdas_plan_destroy.argtypes = [vp]
@@ -205,6 +208,12 @@ class Plan:
     def set_workgroups_per_cu(self, per_cu: int):
         """Cap the persistent grids at per_cu workgroups per CU (0: no cap)."""
         check(self._lib.fdas_plan_set_workgroups_per_cu(self._h, int(per_cu)))
+
+    def set_direct_templates(self, m: int):
+        """Run the m shortest templates (whole blocks of 8) by direct
+        convolution on the matrix cores and the rest by overlap-save
+        (float32 plans; 0: all by overlap-save, -1: the plan's default)."""
+        check(self._lib.fdas_plan_set_direct_templates(self._h, int(m)))
 
     # -- calls --------------------------------------------------------------
     def input_dtype(self):

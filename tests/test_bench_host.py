@@ -46,12 +46,25 @@ def test_measured_traffic_tracks_kernel_source(monkeypatch, tmp_path):
     # a summary carrying the current source hash is used; any other hash,
     # or no summary for the segment length, gives null
     f = tmp_path / "traffic.md"
-    f.write_text(f"kernel_source_sha: {bench.kernel_source_hash()}\n\ntraffic_bytes_per_launch: 1.488765e+09\n")
-    monkeypatch.setattr(bench, "TRAFFIC_FILES", {2048: str(f)})
-    assert bench.measured_traffic(2048) == 1.488765e9
-    assert bench.measured_traffic(1024) is None
+    f.write_text(f"kernel_source_sha: {bench.kernel_source_hash()}\n\ntraffic_bytes_per_call: 1.488765e+09\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {(2048, 56): str(f)})
+    assert bench.measured_traffic(2048, 56) == 1.488765e9
+    assert bench.measured_traffic(2048, 0) is None          # another split
+    assert bench.measured_traffic(1024, 56) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic(2048) is None
+    assert bench.measured_traffic(2048, 56) is None
+
+
+def test_direct_mfma_operations():
+    # blocks of 8 in order of tap count; per 16 outputs a block issues
+    # 3 x ceil(K_block / 16) products of 16 x 16 x 32 (2 x 8192 operations)
+    lens = [17, 19, 33, 33, 40, 41, 48, 49, 80, 3]
+    n = 100                                                # 7 tiles of 16
+    per = 3 * 2 * 16 * 16 * 32
+    # sorted: 3 17 19 33 33 40 41 48 | 49 80 -> blocks of 48 and 80 taps
+    assert bench.direct_mfma_flops(n, lens, 10) == 7 * per * (3 + 5)
+    assert bench.direct_mfma_flops(n, lens, 8) == 7 * per * 3
+    assert bench.direct_mfma_flops(n, lens, 0) == 0
 
 
 def test_more_than_one_gpu_is_refused():
