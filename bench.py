@@ -36,9 +36,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector: 256 CU x 6
 # 2 (FMA) x 2.4 GHz.
 FP32_UNPACKED_PEAK_TFLOPS = 78.6
 FP16_MFMA_PEAK_TFLOPS = 2500.0        # MI355X published dense binary16 matrix-core peak
-SQ_COUNTER_FILES = {L: os.path.join(ROOT, "profiles", f"fdfir_fused_ska-85x2^22_L{L}_sq_counters.md")
-                    for L in (1024, 2048)}
+SQ_COUNTER_FILES = {2048: os.path.join(ROOT, "profiles", "fdas_convolve_ska-85x2^22_L2048_sq_counters.md")}
 SUSTAINED_S = 1.5                     # back-to-back calls timed for the sustained rate
+SETTLE_S = 0.3                        # untimed back-to-back calls before the timed steps
 KERNEL_SOURCES = ("paper_1805_12280_amd/csrc/seg_fft.h", "paper_1805_12280_amd/csrc/fdas_internal.h",
                   "paper_1805_12280_amd/csrc/fdas_kernels.hip", "paper_1805_12280_amd/csrc/fdas_direct.hip")
 # HBM traffic summaries of one fdas_convolve call, keyed by (segment length,
@@ -74,19 +74,30 @@ def measured_traffic(L, md=0):
     return float(m_bytes.group(1))
 
 
-def measured_valu_issue(L):
-    """VALU issue rate (wave64 instructions per CU per cycle) of the fused
-    kernel from the committed SQ-counter summary for this segment length, if
-    it was taken on the current kernel source; else None."""
+def _sq_line(L, key):
+    """A `key: value` line of the committed SQ-counter summary for this
+    segment length, if it was taken on the current kernel source; else None."""
     path = SQ_COUNTER_FILES.get(L)
     if path is None or not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
-    m_issue = re.search(r"valu_issue_per_cu_cycle:\s*([0-9.eE+]+)", text)
-    if not (m_hash and m_issue) or m_hash.group(1) != kernel_source_hash():
+    m_val = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_val) or m_hash.group(1) != kernel_source_hash():
         return None
-    return float(m_issue.group(1))
+    return float(m_val.group(1))
+
+
+def measured_valu_issue(L, md=0):
+    """VALU issue rate (wave64 instructions per CU per cycle) of the
+    overlap-save launch at this split, from the committed SQ counters."""
+    return _sq_line(L, f"valu_issue_per_cu_cycle[direct={md}]")
+
+
+def measured_mfma_busy(L, md):
+    """Matrix-core busy fraction of the direct launch at this split, from the
+    committed SQ counters."""
+    return _sq_line(L, f"mfma_busy[direct={md}]")
 
 
 def algorithmic_bytes(n, m, L):
@@ -105,18 +116,25 @@ def nominal_flops(n, m, L, k_max):
     return s * (m * (fft + 6 * L + 3 * v) + fft)
 
 
-def time_calls(torch, fn, steps, warmup):
+def time_calls(torch, fn, steps, warmup, mark=None):
+    """Mean ms per call over `steps` calls between two events, after `warmup`
+    untimed calls; synchronised on both sides.  `mark` names a marker range
+    around the timed calls (a profiler's marker trace picks them out)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
+    if mark:
+        torch.cuda.nvtx.range_push(mark)
     start.record(stream)
     for _ in range(steps):
         fn()
     stop.record(stream)
     torch.cuda.synchronize()
+    if mark:
+        torch.cuda.nvtx.range_pop()
     return start.elapsed_time(stop) / steps
 
 
@@ -135,6 +153,16 @@ def time_steps(torch, fn, steps, warmup):
     torch.cuda.synchronize()
     per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
     return ev[0].elapsed_time(ev[steps]) / steps, per
+
+
+def settle(torch, fn, seconds=SETTLE_S):
+    """Back-to-back untimed calls for about `seconds`."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
 
 
 def sustained(torch, fn, ms_hint, seconds=SUSTAINED_S):
@@ -273,14 +301,15 @@ def split_legs(torch, fdas, w, x, L, md, steps, warmup):
                       input_len=n, seg_fft=L)
         p.set_direct_templates(len(idx) if name == "direct" else 0)
         o = torch.empty((len(idx), n), dtype=torch.float32, device=x.device)
-        t = time_calls(torch, lambda: p.convolve(x, out=o), steps, warmup)
+        t = time_calls(torch, lambda: p.convolve(x, out=o), steps, warmup, mark=f"split leg {name}")
         by = 8 * n + 4 * len(idx) * n
         ent = {"templates": len(idx), "ms": t, "hbm_gbs": by / (t * 1e-3) / 1e9,
                "hbm_frac": by / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
         if name == "direct":
             fl = direct_mfma_flops(n, w.bank.tap_len, len(idx))
             ent.update({"mfma_tflops": fl / (t * 1e-3) / 1e12, "mfma_peak_tflops": FP16_MFMA_PEAK_TFLOPS,
-                        "mfma_frac": fl / (t * 1e-3) / 1e12 / FP16_MFMA_PEAK_TFLOPS})
+                        "mfma_frac": fl / (t * 1e-3) / 1e12 / FP16_MFMA_PEAK_TFLOPS,
+                        "mfma_busy_counter": measured_mfma_busy(L, md)})
         else:
             fl = nominal_flops(n, len(idx), L, w.bank.k_max)
             ent.update({"tflops": fl / (t * 1e-3) / 1e12, "peak_tflops": FP32_UNPACKED_PEAK_TFLOPS,
@@ -504,6 +533,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seg-fft", type=int, default=0,
                     help="segment length; 0 = pick with the autotuner among 1024/2048/4096")
+    ap.add_argument("--direct", type=int, default=None,
+                    help="templates run by direct convolution (whole blocks of 8; -1 = the plan's "
+                         "default); default: the autotuner's pick, or the plan's default with --seg-fft")
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-collection run: the plan, W warmup and K timed fdas_convolve calls, "
+                         "nothing else (every direct and overlap-save launch is a headline call)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tdfir", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -552,11 +587,28 @@ def main():
     if not args.seg_fft:
         plan.set_workgroups_per_cu(wg)
         plan.set_direct_templates(direct)
+    if args.direct is not None:
+        plan.set_direct_templates(args.direct)
     out = torch.empty((m, n), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log(f"plan: {plan.info.as_dict()} variant={plan.variant}")
 
-    ms, per_step = time_steps(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup)
+    # untimed back-to-back calls first, so the timed steps see the clock the
+    # chip holds under load rather than the idle clock after the tuning;
+    # then exactly K steps between two events, and the per-call spread in a
+    # pass of its own (events between calls add a small gap to each call)
+    if args.counters:
+        ms = time_calls(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup)
+        log(f"counters run: {args.warmup} + {args.steps} calls, {ms:.4f} ms/call, "
+            f"direct templates {plan.info.direct_templates}")
+        print(json.dumps({"counters_run": True, "ms_per_step": ms, "seg_fft": L,
+                          "direct_templates": plan.info.direct_templates}), flush=True)
+        plan.close()
+        return
+    settle(torch, lambda: plan.convolve(x, out=out))
+    ms = time_calls(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup,
+                    mark="fdas_convolve timed steps")
+    _, per_step = time_steps(torch, lambda: plan.convolve(x, out=out), args.steps, 0)
     value = m * n / (ms * 1e-3)
     abytes = algorithmic_bytes(n, m, L)
     achieved = abytes / (ms * 1e-3) / 1e9
@@ -601,7 +653,7 @@ def main():
         "alu_roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_UNPACKED_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": tflops / FP32_UNPACKED_PEAK_TFLOPS,
                          "published_fp32_vector_peak": FP32_VECTOR_PEAK_TFLOPS,
-                         "valu_issue_per_cu_cycle": measured_valu_issue(L)},
+                         "valu_issue_per_cu_cycle": measured_valu_issue(L, md)},
         "launches": kernels,
         "step_ms": percentiles(per_step),
     }

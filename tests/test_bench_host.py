@@ -74,14 +74,20 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def test_measured_valu_issue_tracks_kernel_source(monkeypatch, tmp_path):
+def test_measured_counters_track_kernel_source_and_split(monkeypatch, tmp_path):
     f = tmp_path / "sq.md"
-    f.write_text(f"kernel_source_sha: {bench.kernel_source_hash()}\n\nvalu_issue_per_cu_cycle: 0.93\n")
+    f.write_text(f"kernel_source_sha: {bench.kernel_source_hash()}\n\n"
+                 "valu_issue_per_cu_cycle[direct=0]: 0.967\nmfma_busy[direct=40]: 0.64\n"
+                 "valu_issue_per_cu_cycle[direct=40]: 0.929\n")
     monkeypatch.setattr(bench, "SQ_COUNTER_FILES", {2048: str(f)})
-    assert bench.measured_valu_issue(2048) == 0.93
-    assert bench.measured_valu_issue(1024) is None
+    assert bench.measured_valu_issue(2048, 0) == 0.967
+    assert bench.measured_valu_issue(2048, 40) == 0.929
+    assert bench.measured_mfma_busy(2048, 40) == 0.64
+    assert bench.measured_valu_issue(2048, 56) is None       # no line for that split
+    assert bench.measured_mfma_busy(2048, 0) is None
+    assert bench.measured_valu_issue(1024, 0) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_valu_issue(2048) is None
+    assert bench.measured_valu_issue(2048, 0) is None
 
 
 def test_unpacked_fp32_peak_from_unit_counts():
