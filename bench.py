@@ -339,6 +339,7 @@ def batched_leg(torch, fdas, steps, warmup):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=side):
         plan.convolve_batched(dev, topk=16, out=out, workspace=ws)
+    settle(torch, g.replay)
     ms = time_calls(torch, g.replay, steps, warmup)
     m = bank.num_templates
     samples = m * sum(batch.lengths)
@@ -348,8 +349,8 @@ def batched_leg(torch, fdas, steps, warmup):
     res = {"workload": batch.name, "arrays": len(dev), "points": sum(batch.lengths),
            "topk": 16, "seg_fft": best, "workgroups_per_cu": wg, "autotune_ms": tuned, "graph": True,
            "ms_per_step": ms, "value": samples / (ms * 1e-3), "unit": "template-samples/s",
-           "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS}}
+           "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_UNPACKED_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": tflops / FP32_UNPACKED_PEAK_TFLOPS}}
     # the same batch on the 16-bit plans (L = 2048), also graph-replayed
     for prec in ("fp16", "bf16"):
         plan = fdas.Plan(bank.taps, bank.tap_len, input_len=max(batch.lengths), seg_fft=2048, precision=prec)
@@ -359,6 +360,7 @@ def batched_leg(torch, fdas, steps, warmup):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=side):
             plan.convolve_batched(dev16, topk=16, out=out, workspace=ws)
+        settle(torch, g.replay)
         ms16 = time_calls(torch, g.replay, steps, warmup)
         res[prec] = {"ms_per_step": ms16, "value": samples / (ms16 * 1e-3), "speedup_vs_fp32": ms / ms16,
                      "workspace_bytes": int(ws.numel())}
@@ -471,6 +473,7 @@ def mixed_leg(torch, fdas, w, x32, P32, steps, warmup, fp32_ms):
     for prec in ("fp16", "bf16"):
         plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=2048, precision=prec)
         xh = torch.view_as_real(x32).to(plan.input_dtype()).contiguous()
+        settle(torch, lambda: plan.convolve(xh, out=out))
         ms = time_calls(torch, lambda: plan.convolve(xh, out=out), steps, warmup)
         dev = float(((out - P32).abs().max() / peak).item())
         rr = float((torch.linalg.vector_norm((out - P32).flatten().double())
@@ -539,6 +542,8 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: the plan, W warmup and K timed fdas_convolve calls, "
                          "nothing else (every direct and overlap-save launch is a headline call)")
+    ap.add_argument("--counters-precision", choices=("fp32", "fp16", "bf16"), default="fp32",
+                    help="with --counters: the plan's precision (16-bit plans at L = 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tdfir", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -597,6 +602,16 @@ def main():
     # chip holds under load rather than the idle clock after the tuning;
     # then exactly K steps between two events, and the per-call spread in a
     # pass of its own (events between calls add a small gap to each call)
+    if args.counters and args.counters_precision != "fp32":
+        plan.close()
+        plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=2048, precision=args.counters_precision)
+        xh = torch.view_as_real(x).to(plan.input_dtype()).contiguous()
+        ms = time_calls(torch, lambda: plan.convolve(xh, out=out), args.steps, args.warmup)
+        log(f"counters run ({args.counters_precision}): {args.warmup} + {args.steps} calls, {ms:.4f} ms/call")
+        print(json.dumps({"counters_run": True, "precision": args.counters_precision, "ms_per_step": ms}),
+              flush=True)
+        plan.close()
+        return
     if args.counters:
         ms = time_calls(torch, lambda: plan.convolve(x, out=out), args.steps, args.warmup)
         log(f"counters run: {args.warmup} + {args.steps} calls, {ms:.4f} ms/call, "
