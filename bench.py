@@ -340,7 +340,7 @@ def batched_leg(torch, fdas, steps, warmup):
     with torch.cuda.graph(g, stream=side):
         plan.convolve_batched(dev, topk=16, out=out, workspace=ws)
     settle(torch, g.replay)
-    ms = time_calls(torch, g.replay, steps, warmup)
+    ms = time_calls(torch, g.replay, steps, warmup, mark="batched fp32 timed steps")
     m = bank.num_templates
     samples = m * sum(batch.lengths)
     flops = sum(nominal_flops(n, m, best, bank.k_max) for n in batch.lengths)
@@ -361,7 +361,7 @@ def batched_leg(torch, fdas, steps, warmup):
         with torch.cuda.graph(g, stream=side):
             plan.convolve_batched(dev16, topk=16, out=out, workspace=ws)
         settle(torch, g.replay)
-        ms16 = time_calls(torch, g.replay, steps, warmup)
+        ms16 = time_calls(torch, g.replay, steps, warmup, mark=f"batched {prec} timed steps")
         res[prec] = {"ms_per_step": ms16, "value": samples / (ms16 * 1e-3), "speedup_vs_fp32": ms / ms16,
                      "workspace_bytes": int(ws.numel())}
         log(f"batched {prec}: {ms16:.3f} ms/step ({ms / ms16:.2f}x fp32)")
@@ -474,7 +474,7 @@ def mixed_leg(torch, fdas, w, x32, P32, steps, warmup, fp32_ms):
         plan = fdas.Plan(w.bank.taps, w.bank.tap_len, input_len=n, seg_fft=2048, precision=prec)
         xh = torch.view_as_real(x32).to(plan.input_dtype()).contiguous()
         settle(torch, lambda: plan.convolve(xh, out=out))
-        ms = time_calls(torch, lambda: plan.convolve(xh, out=out), steps, warmup)
+        ms = time_calls(torch, lambda: plan.convolve(xh, out=out), steps, warmup, mark=f"mixed {prec} timed steps")
         dev = float(((out - P32).abs().max() / peak).item())
         rr = float((torch.linalg.vector_norm((out - P32).flatten().double())
                     / torch.linalg.vector_norm(P32.flatten().double())).item())

@@ -241,3 +241,32 @@ def test_split_requests(torch_cuda, fdas):
     with pytest.raises(fdas.FdasError):
         p16.set_direct_templates(8)
     p16.close()
+
+
+def test_split_call_in_a_graph(torch_cuda, fdas):
+    """Both launches of a split call captured in a HIP graph: every replay
+    (with eager calls on the plan between them) equals the eager plane bit
+    for bit."""
+    torch = torch_cuda
+    bank = ragged_bank(23, 20, 110)
+    n = 50000
+    x_np, _ = datagen.random_case(24, n, 1, 1)
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n, seg_fft=1024)
+    plan.set_direct_templates(16)
+    assert plan.info.direct_templates == 16
+    x = torch.from_numpy(x_np).cuda()
+    eager = plan.convolve(x).clone()
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.convolve(x, out=out)
+    for rep in range(3):
+        out.fill_(-1.0)
+        _ = plan.convolve(x[: n // 2].contiguous())     # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+    plan.close()
