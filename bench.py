@@ -51,11 +51,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(text: str) -> str:
+    """Source text with comments, trailing blanks and empty lines removed, so
+    a comment-only edit leaves the kernel's hash unchanged."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def kernel_source_hash() -> str:
+    """First 16 hex digits of sha256 over the float32 path's sources (code
+    only): the committed counter summaries carry the value they were taken
+    on."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -25,7 +25,7 @@
 // so lane (j, g = l / 16) reads four consecutive complex inputs x[..+4g..]
 // for its B operand, and holds Re/Im of templates 2g and 2g + 1 for output
 // j.  A block's tap operands take 8 NK registers and a tile's accumulator
-// 4, so a wave keeps them all in registers at 4 waves per SIMD.
+// 4, so a wave keeps them all in registers at 3 waves per SIMD.
 //
 // Float32-class accuracy from binary16 operands: every operand v (scaled by a
 // power of two so |v| < 2^14) is split v = hi + lo with hi = fp16(v) and
@@ -183,7 +183,7 @@ __device__ __forceinline__ void run_block(const uint4 *__restrict__ A, const int
 // Grid: one wave per 512 outputs, kWaves waves per workgroup.  Each wave
 // stages x[o0 - kpmax + 1, o0 + 512) (zero outside [0, n)) in its own LDS
 // rows, scaled by 2^sx (so every component is below 2^14) and split into
-// binary16 high and low parts, then runs every direct block over its 16
+// binary16 high and low parts, then runs every direct block over its 32
 // tiles.  blocks: [nblk] steps of 16 taps; A: the blocks' split tap
 // operands, block b at aoff[b] (uint4 units): for step k, 64 lanes of hi
 // then 64 of lo; rows/pexp: [nblk][8] plane row (-1 for padding) and -2 x

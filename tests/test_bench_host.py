@@ -94,3 +94,12 @@ def test_unpacked_fp32_peak_from_unit_counts():
     # one wave64 FMA instruction per CU per cycle: 256 CUs x 64 lanes x 2 x 2.4 GHz
     assert abs(256 * 64 * 2 * 2.4e9 / 1e12 - bench.FP32_UNPACKED_PEAK_TFLOPS) < 0.1
     assert abs(2 * bench.FP32_UNPACKED_PEAK_TFLOPS - bench.FP32_VECTOR_PEAK_TFLOPS) < 0.2
+
+
+def test_kernel_hash_ignores_comments_only():
+    # comments, trailing blanks and empty lines do not count; code does
+    a = "int f(int x) {  // doubles\n    return 2 * x;   \n}\n\n/* note */\n"
+    b = "// header\nint f(int x) {\n    return 2 * x;\n}\n"
+    c = "int f(int x) {\n    return 3 * x;\n}\n"
+    assert bench.code_text(a) == bench.code_text(b)
+    assert bench.code_text(a) != bench.code_text(c)
