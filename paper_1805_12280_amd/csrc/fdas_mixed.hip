@@ -379,15 +379,9 @@ template <bool BF> struct MixLane {
     // pass C, columns j = 16 (4w + gam) + col: radix 16 over k1.  The
     // operand is read from bb, then each half h of the outputs is one
     // product whose rows are outputs m = 8h + 2g + i (re, im)
-    // Four single-word reads (k1 = 4g .. 4g + 3 sit 4 words apart), each
-    // taking the 64 banks once over the wave, which is the access the
-    // bank-conflict check of these maps models; the compiler would otherwise
-    // pair them into two-word reads (measured 1% slower).  Volatile LDS
-    // reads are issued one by one, in order.
     __device__ __forceinline__ uint4 pass_c_operand(const uint32_t *bbr, int gam) const
     {
-        typedef const volatile __attribute__((address_space(3))) uint32_t lds_word;
-        lds_word *src = (lds_word *)(bbr + 4 * gam * mix::BJ);
+        const uint32_t *src = bbr + 4 * gam * mix::BJ;
         return make_uint4(src[0], src[4], src[8], src[12]);
     }
     __device__ __forceinline__ f4v pass_c(int h, uint4 bop) const
