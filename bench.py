@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "template-samples/s (85 tpl x 2^22 pts) + HBM roofline frac; served p50/p99 ms"
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector: 256 CU x 64 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
-# What this build can issue: packed FP32 is off in every device compile, so at
+# What the library's kernels can issue: packed FP32 is off in every device compile, so at
 # most one wave64 VALU instruction per CU per cycle, i.e. 256 CU x 64 lanes x
 # 2 (FMA) x 2.4 GHz.
 FP32_UNPACKED_PEAK_TFLOPS = 78.6
@@ -672,7 +672,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": abytes},
         # the overlap-save launch priced as arithmetic: nominal FFT operations
-        # of all templates against the FP32 FMA peak this build can issue (no
+        # of all templates against the FP32 FMA peak the kernels can issue (no
         # packed FP32), with the VALU issue rate read from the committed SQ
         # counters; with a direct split, the per-launch figures are in
         # "launches"
