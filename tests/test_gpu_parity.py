@@ -250,6 +250,31 @@ def test_plane_past_2g_elements_sampled(torch_cuda, fdas, large, prec, method, L
     plan.close()
 
 
+def test_direct_rows_past_2g_elements_sampled(torch_cuda, fdas, large):
+    """The direct-convolution route writing rows whose offsets pass 2^31
+    elements: with the bank in order of decreasing tap count, the plan's
+    shortest templates (the ones it runs directly) are its last rows."""
+    torch = torch_cuda
+    w, _, wins, _, _, x, out = large
+    order = np.argsort(-w.bank.tap_len, kind="stable")
+    taps, tl = np.ascontiguousarray(w.bank.taps[order]), np.ascontiguousarray(w.bank.tap_len[order])
+    m, n = len(tl), w.n
+    plan = fdas.Plan(taps, tl, input_len=n, seg_fft=2048)
+    md = plan.info.direct_templates
+    _say(f"[large] 85 x {n} fp32, rows by decreasing tap count, {md} direct")
+    assert md > 0 and (m - 1) * n > 2 ** 31
+    rows = sorted({0, m - md - 1, m - md, m - md // 2, m - 2, m - 1})
+    refs = [oracle.power(w.x, taps, tl, rows=rows, i0=a, i1=b) for a, b in wins]
+    peak = max(float(r.max()) for r in refs)
+    out.fill_(-7.0)
+    plan.convolve(x, out=out)
+    torch.cuda.synchronize()
+    err = max(float(np.abs(out[rows, a:b].cpu().numpy() - r).max()) for (a, b), r in zip(wins, refs))
+    _say(f"  max err / sampled peak {err / peak:.3e}")
+    assert err <= FP32_TOL * peak, err / peak
+    plan.close()
+
+
 @pytest.mark.parametrize("L", [1024, 2048])
 def test_paper_shape_84_filters_421_taps(torch_cuda, fdas, L):
     """The paper's studied bank shape (84 complex filters of 421 taps,
