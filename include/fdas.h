@@ -105,9 +105,9 @@ typedef struct {
  *              and binary16 keeps 11 significant bits against bfloat16's 8);
  *              the power plane is float32.  The template spectra (scaled by a
  *              power of two so their largest component is in [1/2, 1)) are
- *              stored as binary16 for FDAS_FP16, where Z = X H is formed in
- *              packed binary16 arithmetic, and as float32 for FDAS_BF16, where
- *              Z = X H is formed in float32 and rounded once.  Mixed plans need
+ *              stored as binary16 and Z = X H is formed in packed binary16
+ *              arithmetic; the two flags differ only in the input format.
+ *              Mixed plans need
  *              seg_fft = 2048 (or 0) and support fdas_convolve and
  *              fdas_convolve_batched; fdas_tdfir and fdas_segment_fft
  *              return FDAS_EUNSUPPORTED.  A mixed plan also

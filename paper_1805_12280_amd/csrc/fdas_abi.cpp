@@ -64,7 +64,7 @@ struct fdas_plan {
     int fused_per_cu = 1;
     int mixed_per_cu = 1;
     int eh = 0;                // template spectra scaled by 2^eh in 16-bit storage
-    void *d_H16 = nullptr;     // [M][2048] template spectra, pass-A lane order (binary16 pairs, or float32 for BF16)
+    void *d_H16 = nullptr;     // [M][2048] template spectra, pass-A lane order (binary16 pairs)
     void *d_mat = nullptr;     // 16-bit DFT matrices of the inverse passes
     void *d_stage = nullptr;   // scaled segment spectra of one call (16-bit plans)
     hipEvent_t stage_free = nullptr;  // recorded after each call that used d_stage
@@ -323,7 +323,7 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
         int ex = 0;
         if (mx > 0.f) std::frexp(mx, &ex);           // mx < 2^ex
         p->eh = -ex;
-        const size_t bytes16 = fdas::mixed_spectra_bytes(prec == 2, M);
+        const size_t bytes16 = fdas::mixed_spectra_bytes(M);
         const size_t stage = fdas::mixed_stage_bytes(p->g.segments(input_len));
         e = hipMalloc((void **)&p->d_H16, bytes16);
         if (e == hipSuccess) e = hipMalloc(&p->d_mat, fdas::mixed_matrix_bytes());
@@ -331,13 +331,12 @@ FDAS_API int fdas_plan_create(fdas_plan **out, const void *taps, const int32_t *
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->stage_free, hipEventDisableTiming);
         if (e == hipSuccess) e = fdas::launch_mat_table(p->d_mat, st);
         if (e == hipSuccess)
-            e = fdas::launch_tspec_mix(p->d_taps, p->d_tap_len, kp, M, std::ldexp(1.f, p->eh), prec == 2,
-                                       p->d_H16, st);
+            e = fdas::launch_tspec_mix(p->d_taps, p->d_tap_len, kp, M, std::ldexp(1.f, p->eh), p->d_H16, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) { free_plan(p); return hip_fail(e, "building 16-bit template spectra"); }
         p->resident_bytes += (int64_t)(bytes16 + fdas::mixed_matrix_bytes() + stage);
-        p->mixed_per_cu = fdas::mixed_blocks_per_cu(prec == 2);
-        p->g.topk_fit = fdas::mixed_topk_blocks_per_cu(prec == 2);
+        p->mixed_per_cu = fdas::mixed_blocks_per_cu();
+        p->g.topk_fit = fdas::mixed_topk_blocks_per_cu();
     }
     *out = p;
     return FDAS_OK;

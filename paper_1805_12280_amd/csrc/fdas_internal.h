@@ -83,7 +83,7 @@ struct MixedArgs {
     const void *mat;      // DFT matrices of the three passes (mixed_matrix_bytes())
     const c32 *twL;
     int M, D, V, eh;
-    bool bf;
+    bool bf;              // input pairs are bfloat16 (else binary16)
     int64_t items, grid;
     int64_t segments;     // ceil(n / V)
     void *stage;          // mixed_stage_bytes(segments): scaled spectra and power scales
@@ -102,10 +102,10 @@ size_t tdfir_lds_bytes(int kp, int tg);
 size_t fused_lds_bytes(int L);              // LDS of the float32 template-loop kernels at segment length L
 int tdfir_group(int kp, int M);              // largest template group whose taps fit TD_TAP_BYTES
 int topk_blocks_per_cu(int L);
-hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
-                            void *H16, hipStream_t st);
-size_t mixed_spectra_bytes(bool bf, int M);  // template spectra of a 16-bit plan
-int mixed_blocks_per_cu(bool bf);
+hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, void *H16,
+                            hipStream_t st);
+size_t mixed_spectra_bytes(int M);           // template spectra of a 16-bit plan (binary16)
+int mixed_blocks_per_cu();
 size_t mixed_matrix_bytes();
 hipError_t launch_mat_table(void *tab, hipStream_t st);
 hipError_t launch_mixed(const MixedArgs &a, hipStream_t st);
@@ -120,7 +120,7 @@ struct MixedTopkArgs {
     const void *H16, *mat;
     const c32 *twL;
     int M, D, V, K, eh;
-    bool bf;
+    bool bf;              // input pairs are bfloat16 (else binary16)
     int64_t items, grid, segments;
     void *xstage;         // mixed_stage_bytes(segments)
     void *stage, *hdr;
@@ -128,7 +128,7 @@ struct MixedTopkArgs {
     int max_slots;
     void *out;
 };
-int mixed_topk_blocks_per_cu(bool bf);
+int mixed_topk_blocks_per_cu();
 hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st);
 hipError_t launch_tdfir(const TdArgs &a, hipStream_t st);
 

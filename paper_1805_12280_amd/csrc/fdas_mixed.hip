@@ -4,19 +4,17 @@
 //
 // Both plans feed the matrix cores binary16 operands: each segment is scaled
 // by a power of two, so the 5 exponent bits of binary16 suffice and its 11
-// significant bits keep 3 more than bfloat16's 8.  An FP16 plan stores the
-// template spectra as binary16 and forms Z = X H in packed binary16
-// arithmetic; a BF16 plan (bfloat16 input) keeps the template spectra in
-// float32 and forms Z = X H in float32, rounding it once to binary16, so the
-// arithmetic adds no more than one 11-bit rounding per operand of each pass.
+// significant bits keep 3 more than bfloat16's 8.  Both store the template
+// spectra as binary16 and form Z = X H in packed binary16 arithmetic; they
+// differ only in the input format the forward launch reads.
 //
 // Two launches per call.  Per segment (mixed_fwd_kernel, float32 VALU):
 // gather the 16-bit input, forward FFT (seg_fft.h), redistribute the
 // spectrum X into the lanes that feed pass A (mixed_fft.h), pick a
 // power-of-two scale sigma from max |X| so the 16-bit operands stay well
 // inside their range, and stage sigma X.  Per (segment, template)
-// (fdfir_mixed_kernel): Z = sigma X H rounded once to 16 bits, passes A, B,
-// C as matrix products, |y|^2 unscaled exactly by the powers of two,
+// (fdfir_mixed_kernel): Z = sigma X H in packed binary16 arithmetic, passes
+// A, B, C as matrix products, |y|^2 unscaled exactly by the powers of two,
 // full-line streaming stores.  The batched form (mixed_fwd_batch_kernel,
 // fdfir_mixed_topk_kernel) runs the same passes over many spectra and keeps
 // each one's top-K cells instead of its plane.
@@ -34,10 +32,9 @@ typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Storage type: complex value as a pair of 16-bit numbers in one 32-bit word.
-template <bool BF> struct Half;
-
-template <> struct Half<false> {   // IEEE binary16
+// Matrix-core operands and the elementwise products of the template loop:
+// a complex value as a pair of IEEE binary16 numbers in one 32-bit word.
+struct Half {
     __device__ static uint32_t pack(float re, float im)
     {
         // opaque to the compiler, so the arithmetic that produced re and im
@@ -82,31 +79,14 @@ template <> struct Half<false> {   // IEEE binary16
     }
     // The scaled spectrum and the pass-B twiddles are held as packed
     // binary16 (the products Z = X H and b W run in packed arithmetic).
-    using XReg = uint32_t;
-    using TwReg = uint32_t;
-    __device__ static XReg to_x(float re, float im) { return pack(re, im); }
-    __device__ static TwReg to_tw(float re, float im) { return pack(re, im); }
-    __device__ static uint32_t zmul(XReg x, uint32_t h) { return cmulp(x, h); }
-    __device__ static uint32_t twmul(float re, float im, TwReg w) { return cmulp(pack_acc(re, im), w); }
-};
-
-// The loop policy of a plan whose input is bfloat16: the same binary16
-// operands, matrix products and packed twiddle products as an FP16 plan, with
-// the template spectra held in float32 (ZW = c32 per value) and Z = X H
-// formed in float32 from the binary16-staged X, then rounded once.
-template <> struct Half<true> : Half<false> {
-    __device__ static uint32_t zmul(XReg x, c32 h)
-    {
-        const c32 xv = Half<false>::unpack(x);
-        const c32 z = mul(xv, h);
-        return Half<false>::pack(z.re, z.im);
-    }
+    __device__ static uint32_t zmul(uint32_t x, uint32_t h) { return cmulp(x, h); }
+    __device__ static uint32_t twmul(float re, float im, uint32_t w) { return cmulp(pack_acc(re, im), w); }
 };
 
 // Input formats: a complex value as a pair of 16-bit numbers in one word.
 template <bool BF> struct In16;
 template <> struct In16<false> {
-    __device__ static c32 unpack(uint32_t w) { return Half<false>::unpack(w); }
+    __device__ static c32 unpack(uint32_t w) { return Half::unpack(w); }
 };
 template <> struct In16<true> {
     __device__ static c32 unpack(uint32_t w)
@@ -116,23 +96,11 @@ template <> struct In16<true> {
 };
 
 // Template spectra of one work-item for one template, in the order pass A
-// consumes them (16 values): packed binary16 for an FP16 plan, float32 for a
-// BF16 plan.
-template <bool BF> struct HSpec;
-template <> struct HSpec<false> {
+// consumes them (16 packed binary16 values).
+struct HSpec {
     uint4 q[4];
     __device__ __forceinline__ uint32_t at(int v) const { return (&q[v >> 2].x)[v & 3]; }
 };
-template <> struct HSpec<true> {
-    float4 q[8];
-    __device__ __forceinline__ c32 at(int v) const
-    {
-        const float4 f = q[v >> 1];
-        return (v & 1) ? mk(f.z, f.w) : mk(f.x, f.y);
-    }
-};
-// bytes of one template spectrum value
-constexpr int hspec_bytes(bool bf) { return bf ? 8 : 4; }
 
 // One real matrix entry of exp(2 pi i turns) for interleaved rows/columns.
 __device__ __forceinline__ float wentry(int row, int k, double turns)
@@ -152,9 +120,8 @@ __device__ __forceinline__ float wentry(int row, int k, double turns)
 // template spectra in the lane layout of pass A, 16-bit, scaled by 2^eh
 // ---------------------------------------------------------------------------
 
-template <bool BF>
 __global__ void tspec_mix_kernel(const c32 *__restrict__ taps, const int *__restrict__ tap_len, int kp, int M,
-                                 float scale, void *__restrict__ H16)
+                                 float scale, uint32_t *__restrict__ H16)
 {
     using namespace mix;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,10 +140,7 @@ __global__ void tspec_mix_kernel(const c32 *__restrict__ taps, const int *__rest
         re += hr * c - hi * s;
         im += hr * s + hi * c;
     }
-    if constexpr (BF)
-        reinterpret_cast<c32 *>(H16)[idx] = mk((float)(re / L * scale), (float)(im / L * scale));
-    else
-        reinterpret_cast<uint32_t *>(H16)[idx] = Half<false>::pack((float)(re / L * scale), (float)(im / L * scale));
+    H16[idx] = Half::pack((float)(re / L * scale), (float)(im / L * scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -202,7 +166,7 @@ __global__ void mat_table_kernel(uint4 *__restrict__ tab)
             const int k = 4 * g + e;
             e4[e] = wentry(i, k, mix::turns_A(r, i >> 1, k >> 1));
         }
-        reinterpret_cast<uint2 *>(tab)[idx] = make_uint2(Half<false>::pack(e4[0], e4[1]), Half<false>::pack(e4[2], e4[3]));
+        reinterpret_cast<uint2 *>(tab)[idx] = make_uint2(Half::pack(e4[0], e4[1]), Half::pack(e4[2], e4[3]));
     } else if (idx < MAT_A_UINT2 + 2 * 64) {
         const int h = (idx - MAT_A_UINT2) >> 6, out = 8 * h + (i >> 1);
         float e8[8];
@@ -210,8 +174,8 @@ __global__ void mat_table_kernel(uint4 *__restrict__ tab)
             const int k = 8 * g + e;
             e8[e] = wentry(i, k, mix::turns_D16(out, k >> 1));
         }
-        tab[MAT_D + h * 64 + l] = make_uint4(Half<false>::pack(e8[0], e8[1]), Half<false>::pack(e8[2], e8[3]),
-                                             Half<false>::pack(e8[4], e8[5]), Half<false>::pack(e8[6], e8[7]));
+        tab[MAT_D + h * 64 + l] = make_uint4(Half::pack(e8[0], e8[1]), Half::pack(e8[2], e8[3]),
+                                             Half::pack(e8[4], e8[5]), Half::pack(e8[6], e8[7]));
     }
 }
 
@@ -320,11 +284,11 @@ __global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restri
 // W128^(p r) folded in; the DFT16 of passes B and C) and the pass-B output
 // twiddles W2048^(j k1).  Both template-loop kernels run the passes through
 // these members, so they compute every cell identically.
-template <bool BF> struct MixLane {
-    using HF = Half<BF>;
+struct MixLane {
+    using HF = Half;
     uint2 aA[8];
     uint4 aD[2];
-    typename HF::TwReg twc[4][2][2];
+    uint32_t twc[4][2][2];
 
     __device__ __forceinline__ void init(const uint4 *__restrict__ mat, const c32 *__restrict__ twL, int w, int l)
     {
@@ -341,12 +305,12 @@ template <bool BF> struct MixLane {
                 for (int i = 0; i < 2; ++i) {
                     const int j = 4 * w + gam + 8 * (8 * h + 2 * g + i);
                     const c32 f = twL[(j * col) & (mix::L - 1)];        // exp(-2 pi i j k1 / L)
-                    twc[gam][h][i] = HF::to_tw(f.re, -f.im);
+                    twc[gam][h][i] = HF::pack(f.re, -f.im);
                 }
     }
-    // pass A, column set r = 8w + gam: Z = X H rounded once, radix 8 over s;
+    // pass A, column set r = 8w + gam: Z = X H (packed binary16), radix 8 over s;
     // returns c[2g][col][r] and c[2g + 1][col][r] packed
-    __device__ __forceinline__ void pass_a(const typename HF::XReg (&X)[16], const HSpec<BF> &Hn, int gam,
+    __device__ __forceinline__ void pass_a(const uint32_t (&X)[16], const HSpec &Hn, int gam,
                                            uint32_t &c0, uint32_t &c1) const
     {
         const uint2 bop = make_uint2(HF::zmul(X[2 * gam], Hn.at(2 * gam)), HF::zmul(X[2 * gam + 1], Hn.at(2 * gam + 1)));
@@ -416,30 +380,22 @@ struct MixBases {
 };
 
 // template spectra of template t for work-item tau (its 16 values, contiguous)
-__device__ __forceinline__ void load_h16(const void *__restrict__ H16, int t, int tau, HSpec<false> &Hn)
+__device__ __forceinline__ void load_h16(const void *__restrict__ H16, int t, int tau, HSpec &Hn)
 {
     const uint4 *Ht = reinterpret_cast<const uint4 *>(H16) + ((int64_t)t * mix::L + tau * 16) / 4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) Hn.q[k] = Ht[k];
 }
-__device__ __forceinline__ void load_h16(const void *__restrict__ H16, int t, int tau, HSpec<true> &Hn)
-{
-    const float4 *Ht = reinterpret_cast<const float4 *>(H16) + ((int64_t)t * mix::L + tau * 16) / 2;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) Hn.q[k] = Ht[k];
-}
 
 // staged spectrum of global segment s for work-item tau
-template <bool BF>
-__device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t s, int tau,
-                                         typename Half<BF>::XReg (&X)[16])
+__device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t s, int tau, uint32_t (&X)[16])
 {
     const float4 *src = Xs + s * (mix::L / 2) + tau;
 #pragma unroll
     for (int vp = 0; vp < 8; ++vp) {
         const float4 f = src[vp * mix::T];
-        X[2 * vp] = Half<BF>::to_x(f.x, f.y);
-        X[2 * vp + 1] = Half<BF>::to_x(f.z, f.w);
+        X[2 * vp] = Half::pack(f.x, f.y);
+        X[2 * vp + 1] = Half::pack(f.z, f.w);
     }
 }
 
@@ -449,13 +405,11 @@ __device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t 
 // barrier, pass C of item u (reads bb) and pass A of item u + 1 (writes cc)
 // run interleaved in one phase, so the matrix products of one overlap the
 // vector work of the other.
-template <bool BF>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_kernel(
     const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const void *__restrict__ H16,
     const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int64_t items,
     float *__restrict__ P, int64_t ld)
 {
-    using HF = Half<BF>;
     constexpr int L = mix::L;
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     __shared__ __align__(16) uint32_t bb[mix::BB_WORDS];
@@ -478,15 +432,15 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     const int64_t nb = gridDim.x, b = blockIdx.x;
     const int64_t u0 = items * b / nb, u1 = items * (b + 1) / nb;
     if (u0 >= u1) return;
-    MixLane<BF> ml;
+    MixLane ml;
     ml.init(mat, twL, w, l);
 
     int64_t s = u0 / M;                // segment and template of item u
     int t = (int)(u0 - s * M);
     int64_t sa = s;                    // segment and template of the pass-A item
     int ta = t;
-    HSpec<BF> Hn;                      // template spectra of the pass-A item
-    typename HF::XReg X[16];           // sigma-scaled spectrum of segment sa at zq(w, l, v)
+    HSpec Hn;                          // template spectra of the pass-A item
+    uint32_t X[16];                    // sigma-scaled spectrum of segment sa at zq(w, l, v)
     // advance the pass-A item; its template spectra are in flight from here on
     auto next_a = [&]() {
         if (++ta == M) { ta = 0; ++sa; }
@@ -494,7 +448,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
     };
 
     load_h16(H16, ta, tau, Hn);
-    load_x16<BF>(Xs, sa, tau, X);
+    load_x16(Xs, sa, tau, X);
     float pscale = ps[s];              // 2^-2(e_s + eh) of the pass-A segment
     {
         uint32_t pa[2][8];
@@ -515,7 +469,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
         // pass A runs on stale data and its result is never read)
         const float pscale_u = pscale;
         if (sa != s && u + 1 < u1) {
-            load_x16<BF>(Xs, sa, tau, X);
+            load_x16(Xs, sa, tau, X);
             pscale = ps[sa];
         }
         __syncthreads();
@@ -588,15 +542,13 @@ __global__ __launch_bounds__(128) void mixed_fwd_batch_kernel(BatchSet bs, int M
 // scheme of the float32 batched kernel: a uniform threshold, candidates
 // appended to an LDS list, ranked into the kept list), written to the
 // workspace as one list per array the workgroup touches.
-// (FP16 fits 3 waves per SIMD with a few spills outside the hot loop, which
-// measured 5% faster; BF16, whose products stay in float32, runs best at 2)
-template <bool BF>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3))) void fdfir_mixed_topk_kernel(
+// (3 waves per SIMD with a few spills outside the hot loop, which measured
+// 5% faster than 2)
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_topk_kernel(
     BatchSet bs, const float4 *__restrict__ Xs, const float *__restrict__ ps, const void *__restrict__ H16,
     const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int K, int64_t items,
     Cand *__restrict__ stage, int2 *__restrict__ hdr, int *__restrict__ nslots, int max_slots)
 {
-    using HF = Half<BF>;
     constexpr int L = mix::L, T = mix::T;
     __shared__ __align__(16) uint32_t cc[mix::CC_WORDS];
     // the B->C exchange, and after pass C the candidate list (up to L cells)
@@ -619,7 +571,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
         if (tau == 0) nslots[b] = 0;
         return;
     }
-    MixLane<BF> ml;
+    MixLane ml;
     ml.init(mat, twL, w, l);
 
     // item u: global segment gs = u / M, template t; array a; its segments
@@ -632,8 +584,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
     // the pass-A item u + 1 runs one phase ahead
     int64_t gsa = gs;
     int ta = t;
-    HSpec<BF> Hn;
-    typename HF::XReg X[16];
+    HSpec Hn;
+    uint32_t X[16];
     auto next_a = [&]() {
         if (++ta == M) { ta = 0; ++gsa; }
         load_h16(H16, ta, tau, Hn);
@@ -658,7 +610,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
 
     if (tau == 0) s_cnt = 0;
     load_h16(H16, ta, tau, Hn);
-    load_x16<BF>(Xs, gsa, tau, X);
+    load_x16(Xs, gsa, tau, X);
     float pscale = ps[gs];
     {
         uint32_t pa[2][8];
@@ -673,7 +625,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(BF ? 2 : 3)
         ml.pass_b(xb.ccr, xb.bbw);
         const float pscale_u = pscale;
         if (gsa != gs && u + 1 < u1) {
-            load_x16<BF>(Xs, gsa, tau, X);
+            load_x16(Xs, gsa, tau, X);
             pscale = ps[gsa];
         }
         __syncthreads();
@@ -802,31 +754,28 @@ hipError_t launch_mat_table(void *tab, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t mixed_spectra_bytes(bool bf, int M) { return (size_t)hspec_bytes(bf) * (size_t)M * mix::L; }
+size_t mixed_spectra_bytes(int M) { return sizeof(uint32_t) * (size_t)M * mix::L; }
 
-hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, bool bf,
-                            void *H16, hipStream_t st)
+hipError_t launch_tspec_mix(const c32 *taps, const int *tap_len, int kp, int M, float scale, void *H16,
+                            hipStream_t st)
 {
     const int64_t total = (int64_t)M * mix::L;
     dim3 grid((unsigned)((total + 255) / 256)), blk(256);
-    if (bf) hipLaunchKernelGGL(tspec_mix_kernel<true>, grid, blk, 0, st, taps, tap_len, kp, M, scale, H16);
-    else hipLaunchKernelGGL(tspec_mix_kernel<false>, grid, blk, 0, st, taps, tap_len, kp, M, scale, H16);
+    hipLaunchKernelGGL(tspec_mix_kernel, grid, blk, 0, st, taps, tap_len, kp, M, scale, (uint32_t *)H16);
     return hipGetLastError();
 }
 
-int mixed_blocks_per_cu(bool bf)
+int mixed_blocks_per_cu()
 {
     int nb = 0;
-    hipError_t e = bf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel<true>, 128, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel<false>, 128, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_kernel, 128, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-int mixed_topk_blocks_per_cu(bool bf)
+int mixed_topk_blocks_per_cu()
 {
     int nb = 0;
-    hipError_t e = bf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_topk_kernel<true>, 128, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_topk_kernel<false>, 128, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fdfir_mixed_topk_kernel, 128, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
@@ -835,18 +784,12 @@ hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st)
     float4 *Xs = (float4 *)a.xstage;
     float *ps = (float *)((char *)a.xstage + (size_t)a.segments * mix::L * sizeof(c32));
     const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
-    if (a.bf) {
+    if (a.bf)
         hipLaunchKernelGGL(mixed_fwd_batch_kernel<true>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs, ps);
-        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<true>, gi, blk, 0, st, *a.bs, Xs, ps, a.H16,
-                           a.twL, (const uint4 *)a.mat, a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage,
-                           (int2 *)a.hdr, a.nslots, a.max_slots);
-    } else {
-        hipLaunchKernelGGL(mixed_fwd_batch_kernel<false>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs,
-                           ps);
-        hipLaunchKernelGGL(fdfir_mixed_topk_kernel<false>, gi, blk, 0, st, *a.bs, Xs, ps, a.H16,
-                           a.twL, (const uint4 *)a.mat, a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage,
-                           (int2 *)a.hdr, a.nslots, a.max_slots);
-    }
+    else
+        hipLaunchKernelGGL(mixed_fwd_batch_kernel<false>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs, ps);
+    hipLaunchKernelGGL(fdfir_mixed_topk_kernel, gi, blk, 0, st, *a.bs, Xs, ps, a.H16, a.twL, (const uint4 *)a.mat,
+                       a.M, a.D, a.V, a.K, a.items, (Cand *)a.stage, (int2 *)a.hdr, a.nslots, a.max_slots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_topk_merge(a.stage, a.hdr, a.nslots, (int)a.grid, a.max_slots, a.K, a.bs->count, a.out, st);
@@ -860,17 +803,14 @@ hipError_t launch_mixed(const MixedArgs &a, hipStream_t st)
     float4 *Xs = (float4 *)a.stage;
     float *ps = (float *)((char *)a.stage + (size_t)a.segments * mix::L * sizeof(c32));
     const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
-    if (a.bf) {
+    if (a.bf)
         hipLaunchKernelGGL(mixed_fwd_kernel<true>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,
                            a.eh, Xs, ps);
-        hipLaunchKernelGGL(fdfir_mixed_kernel<true>, gi, blk, 0, st, Xs, ps, a.n, a.H16, a.twL,
-                           (const uint4 *)a.mat, a.M, a.D, a.V, a.items, a.P, a.ld);
-    } else {
+    else
         hipLaunchKernelGGL(mixed_fwd_kernel<false>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,
                            a.eh, Xs, ps);
-        hipLaunchKernelGGL(fdfir_mixed_kernel<false>, gi, blk, 0, st, Xs, ps, a.n, a.H16, a.twL,
-                           (const uint4 *)a.mat, a.M, a.D, a.V, a.items, a.P, a.ld);
-    }
+    hipLaunchKernelGGL(fdfir_mixed_kernel, gi, blk, 0, st, Xs, ps, a.n, a.H16, a.twL, (const uint4 *)a.mat, a.M,
+                       a.D, a.V, a.items, a.P, a.ld);
     return hipGetLastError();
 }
 
