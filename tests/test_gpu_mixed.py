@@ -213,6 +213,31 @@ def test_mixed_zero_input_and_determinism(torch_cuda, fdas, prec):
     plan.close()
 
 
+def test_fp16_and_bf16_plans_share_the_loop(torch_cuda, fdas):
+    """The two plans differ only in the input format their forward launch
+    reads: on an input whose components are exact in both formats
+    (integers up to 255 times 2^-6), their planes and their batched top-16
+    are bitwise equal."""
+    torch = torch_cuda
+    _, bank = datagen.random_case(24, 8, 10, 80)
+    n = 30001
+    rng = np.random.Generator(np.random.PCG64(25))
+    v = rng.integers(-255, 256, size=(n, 2)).astype(np.float32) * np.float32(2.0 ** -6)
+    xs = (v[:, 0] + 1j * v[:, 1]).astype(np.complex64)
+    planes, cands = {}, {}
+    for prec in ("fp16", "bf16"):
+        plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n, seg_fft=2048, precision=prec)
+        xa = to16(torch, xs, prec)
+        assert torch.equal(xa.float().cpu(), torch.from_numpy(v)), prec      # exact in the format
+        planes[prec] = plan.convolve(xa)
+        cands[prec] = plan.convolve_batched([xa, xa[:15000].contiguous()], topk=16)
+        torch.cuda.synchronize()
+        plan.close()
+    assert torch.count_nonzero(planes["fp16"]).item() > 0
+    assert torch.equal(planes["fp16"], planes["bf16"])
+    assert torch.equal(cands["fp16"], cands["bf16"])
+
+
 def test_mixed_plan_errors(torch_cuda, fdas):
     torch = torch_cuda
     x, bank = datagen.random_case(23, 4000, 2, 20)
