@@ -111,7 +111,7 @@ typedef struct {
  *              seg_fft = 2048 (or 0) and support fdas_convolve and
  *              fdas_convolve_batched; fdas_tdfir and fdas_segment_fft
  *              return FDAS_EUNSUPPORTED.  A mixed plan also
- *              holds a staging buffer of 16 KB per segment of input_len for
+ *              holds a staging buffer of 8 KB per segment of input_len for
  *              the scaled segment spectra of one call.
  *   hip_stream stream on which the plan is built; the call waits for that
  *              work before it returns, so the plan is ready on any stream.
@@ -250,7 +250,7 @@ int fdas_batched_workspace_bytes(const fdas_plan *plan, const int64_t *n, int32_
  *              fdas_batched_workspace_bytes(plan, n, count, topk) bytes,
  *              256-byte aligned, owned by the caller; no state is kept in
  *              it between calls.  For a mixed plan it also holds the scaled
- *              spectra of every segment of the batch (16 KB per segment).
+ *              spectra of every segment of the batch (8 KB per segment).
  * Asynchronous on hip_stream (two kernel launches, three for a mixed plan;
  * no copies, no memsets, no allocation), so the call can be captured into
  * a HIP graph.  Calls that share a workspace must not overlap.  A mixed
@@ -277,8 +277,8 @@ int fdas_convolve_batched(const fdas_plan *plan, const void *const *d_in, const 
  * without d_workspace and workspace_bytes; a batch whose workspace
  * (fdas_batched_workspace_bytes) exceeds FDAS_STATIC_WORKSPACE_BYTES returns
  * FDAS_EINVAL and enqueues nothing.  A float32 plan's batch of 64 spectra of
- * up to 2^22 points needs well under 1 MB; a 16-bit plan also stages 16 KB
- * per segment, about 2000 segments (3.8 M points at L = 2048) in all.
+ * up to 2^22 points needs well under 1 MB; a 16-bit plan also stages 8 KB
+ * per segment, about 4000 segments (7.6 M points at L = 2048) in all.
  * Every call on one GPU shares that GPU's array, and no call needs it
  * cleared or leaves state in it that a later call reads: calls that overlap
  * on one GPU (different streams, or a graph replay beside another call) race

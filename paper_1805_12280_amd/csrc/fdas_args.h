@@ -54,7 +54,7 @@ inline int discard_of(int k_max) { return (k_max - 1 + 31) / 32 * 32; }
 
 // Bytes a 16-bit plan stages per call: the scaled forward spectrum of every
 // segment (complex float32) and its power scale.
-inline size_t mixed_stage_bytes(int64_t segments) { return (size_t)segments * (MIXED_L * 8 + sizeof(float)); }
+inline size_t mixed_stage_bytes(int64_t segments) { return (size_t)segments * (MIXED_L * 4 + sizeof(float)); }
 
 // What the checks need to know of a plan.
 struct PlanGeom {

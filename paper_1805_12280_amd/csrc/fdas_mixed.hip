@@ -184,14 +184,15 @@ __global__ void mat_table_kernel(uint4 *__restrict__ tab)
 // ---------------------------------------------------------------------------
 
 // One workgroup transforms the segment of x16 starting at input point base
-// and writes, as float4 (two complex values) per work-item and step,
+// and writes, as two packed binary16 complex values per work-item and step,
 // out[v / 2][tau] = sigma X at the frequencies zq(w, l, v), zq(w, l, v + 1)
-// that work-item tau = 64 w + l feeds to pass A, and *ps = 2^-2(e + eh),
+// that work-item tau = 64 w + l feeds to pass A (rounded once, as pass A
+// takes them), and *ps = 2^-2(e + eh),
 // which undoes both power-of-two scalings of |y|^2 (sigma = 2^e with
 // 2 sigma max|X| <= 16, max over the components of the segment's spectrum).
 template <bool BF>
 __device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16, int64_t n, int64_t base,
-                                               const c32 *__restrict__ twL, int eh, float4 *__restrict__ out,
+                                               const c32 *__restrict__ twL, int eh, uint2 *__restrict__ out,
                                                float *__restrict__ ps)
 {
     using SG = Seg<2048>;
@@ -261,15 +262,16 @@ __device__ __forceinline__ void forward_scaled(const uint32_t *__restrict__ x16,
 #pragma unroll
     for (int vp = 0; vp < 8; ++vp) {
         const c32 z0 = src[17 * vp], z1 = src[17 * vp + 272];
-        out[vp * T + tau] = make_float4(z0.re * sigma, z0.im * sigma, z1.re * sigma, z1.im * sigma);
+        out[vp * T + tau] = make_uint2(Half::pack(z0.re * sigma, z0.im * sigma), Half::pack(z1.re * sigma, z1.im * sigma));
     }
 }
 
-// Staging layout: segment s at Xs + s * L / 2 (float4), its scale at ps[s].
+// Staging layout: segment s at Xs + s * L / 2 (uint2: two packed binary16
+// complex values), its scale at ps[s].
 template <bool BF>
 __global__ __launch_bounds__(128) void mixed_fwd_kernel(const uint32_t *__restrict__ x16, int64_t n,
                                                         const c32 *__restrict__ twL, int D, int V, int eh,
-                                                        float4 *__restrict__ Xs, float *__restrict__ ps)
+                                                        uint2 *__restrict__ Xs, float *__restrict__ ps)
 {
     const int64_t s = blockIdx.x;
     forward_scaled<BF>(x16, n, s * V - D, twL, eh, Xs + s * (mix::L / 2), ps + s);
@@ -388,14 +390,14 @@ __device__ __forceinline__ void load_h16(const void *__restrict__ H16, int t, in
 }
 
 // staged spectrum of global segment s for work-item tau
-__device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t s, int tau, uint32_t (&X)[16])
+__device__ __forceinline__ void load_x16(const uint2 *__restrict__ Xs, int64_t s, int tau, uint32_t (&X)[16])
 {
-    const float4 *src = Xs + s * (mix::L / 2) + tau;
+    const uint2 *src = Xs + s * (mix::L / 2) + tau;
 #pragma unroll
     for (int vp = 0; vp < 8; ++vp) {
-        const float4 f = src[vp * mix::T];
-        X[2 * vp] = Half::pack(f.x, f.y);
-        X[2 * vp + 1] = Half::pack(f.z, f.w);
+        const uint2 f = src[vp * mix::T];
+        X[2 * vp] = f.x;
+        X[2 * vp + 1] = f.y;
     }
 }
 
@@ -406,7 +408,7 @@ __device__ __forceinline__ void load_x16(const float4 *__restrict__ Xs, int64_t 
 // run interleaved in one phase, so the matrix products of one overlap the
 // vector work of the other.
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_kernel(
-    const float4 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const void *__restrict__ H16,
+    const uint2 *__restrict__ Xs, const float *__restrict__ ps, int64_t n, const void *__restrict__ H16,
     const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int64_t items,
     float *__restrict__ P, int64_t ld)
 {
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void f
 // item u is u / M and array a's segments start at item_begin[a] / M.
 template <bool BF>
 __global__ __launch_bounds__(128) void mixed_fwd_batch_kernel(BatchSet bs, int M, const c32 *__restrict__ twL,
-                                                              int D, int V, int eh, float4 *__restrict__ Xs,
+                                                              int D, int V, int eh, uint2 *__restrict__ Xs,
                                                               float *__restrict__ ps)
 {
     const int64_t sg = blockIdx.x;
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(128) void mixed_fwd_batch_kernel(BatchSet bs, int M
 // (3 waves per SIMD with a few spills outside the hot loop, which measured
 // 5% faster than 2)
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void fdfir_mixed_topk_kernel(
-    BatchSet bs, const float4 *__restrict__ Xs, const float *__restrict__ ps, const void *__restrict__ H16,
+    BatchSet bs, const uint2 *__restrict__ Xs, const float *__restrict__ ps, const void *__restrict__ H16,
     const c32 *__restrict__ twL, const uint4 *__restrict__ mat, int M, int D, int V, int K, int64_t items,
     Cand *__restrict__ stage, int2 *__restrict__ hdr, int *__restrict__ nslots, int max_slots)
 {
@@ -781,8 +783,8 @@ int mixed_topk_blocks_per_cu()
 
 hipError_t launch_mixed_topk(const MixedTopkArgs &a, hipStream_t st)
 {
-    float4 *Xs = (float4 *)a.xstage;
-    float *ps = (float *)((char *)a.xstage + (size_t)a.segments * mix::L * sizeof(c32));
+    uint2 *Xs = (uint2 *)a.xstage;
+    float *ps = (float *)((char *)a.xstage + (size_t)a.segments * mix::L * sizeof(uint32_t));
     const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
     if (a.bf)
         hipLaunchKernelGGL(mixed_fwd_batch_kernel<true>, gf, blk, 0, st, *a.bs, a.M, a.twL, a.D, a.V, a.eh, Xs, ps);
@@ -799,9 +801,9 @@ static_assert(mix::L == MIXED_L, "staging size of the 16-bit plans (mixed_stage_
 
 hipError_t launch_mixed(const MixedArgs &a, hipStream_t st)
 {
-    // stage: [segments][L] complex float32, then [segments] float
-    float4 *Xs = (float4 *)a.stage;
-    float *ps = (float *)((char *)a.stage + (size_t)a.segments * mix::L * sizeof(c32));
+    // stage: [segments][L] packed binary16 complex, then [segments] float
+    uint2 *Xs = (uint2 *)a.stage;
+    float *ps = (float *)((char *)a.stage + (size_t)a.segments * mix::L * sizeof(uint32_t));
     const dim3 gf((unsigned)a.segments), blk(128), gi((unsigned)a.grid);
     if (a.bf)
         hipLaunchKernelGGL(mixed_fwd_kernel<true>, gf, blk, 0, st, (const uint32_t *)a.x, a.n, a.twL, a.D, a.V,

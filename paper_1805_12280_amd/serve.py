@@ -217,11 +217,11 @@ class GpuExecutor:
     def footprint(self, bank, n):
         # the spectrum while it is admitted, its share of the batch workspace
         # (bounded by one candidate list per workgroup, plus for a 16-bit plan
-        # the staged spectra: 16 KB per segment of about 1900 points), and
+        # the staged spectra: 8 KB per segment of about 1900 points), and
         # its candidates
         if self.precision == "fp32":
             return 8 * int(n) + 64 * 1024 + 12 * self.topk
-        return 4 * int(n) + 9 * int(n) + 80 * 1024 + 12 * self.topk
+        return 4 * int(n) + 5 * int(n) + 80 * 1024 + 12 * self.topk
 
     def start(self, bank, jobs):
         torch = self.torch

@@ -210,7 +210,7 @@ static void batch_args()
         CHECK(fdas::check_static_workspace(s) == (s.bytes <= FDAS_STATIC_WORKSPACE_BYTES ? FDAS_OK : FDAS_EINVAL));
     }
     // the static workspace: a float32 DM-trial batch fits, a 16-bit batch of
-    // 2^22 points (2185 staged segments of 16 KB) does not
+    // two 2^22-point spectra (4370 staged segments of 8 KB) does not
     {
         PlanGeom h;
         CHECK(fdas::check_plan_args(&dummy, 85, 101, int64_t(1) << 22, 2048, 0, h) == FDAS_OK);
@@ -222,6 +222,8 @@ static void batch_args()
         CHECK(s.bytes < (size_t(1) << 20) && fdas::check_static_workspace(s) == FDAS_OK);
         CHECK(fdas::check_plan_args(&dummy, 85, 101, int64_t(1) << 22, 2048, FDAS_FP16, h) == FDAS_OK);
         CHECK(fdas::batch_shape(h, big.data(), 1, 16, s) == FDAS_OK);
+        CHECK(fdas::check_static_workspace(s) == FDAS_OK);
+        CHECK(fdas::batch_shape(h, big.data(), 2, 16, s) == FDAS_OK);
         CHECK(fdas::check_static_workspace(s) == FDAS_EINVAL);
         std::vector<int64_t> small(2, 1 << 20);
         CHECK(fdas::batch_shape(h, small.data(), 2, 16, s) == FDAS_OK);

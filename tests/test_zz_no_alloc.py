@@ -70,9 +70,9 @@ def test_static_workspace_refuses_oversized_batch(env):
     _, bank = datagen.random_case(78, 4, 5, 33)
     plan = fdas.Plan(bank.taps, bank.tap_len, input_len=1 << 22, seg_fft=2048, precision="fp16")
     big = torch.zeros(((1 << 22), 2), dtype=torch.float16, device="cuda")
-    need = plan.batched_workspace_bytes([1 << 22], 16)
+    need = plan.batched_workspace_bytes([1 << 22, 1 << 22], 16)
     assert need > fdas.STATIC_WORKSPACE_BYTES
-    rc, out = call_static(torch, fdas, lib, plan, [big], 16)
+    rc, out = call_static(torch, fdas, lib, plan, [big, big], 16)
     torch.cuda.synchronize()
     assert rc == fdas.FDAS_EINVAL
     assert b"static workspace" in lib.fdas_last_error()
