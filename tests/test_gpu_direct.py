@@ -107,6 +107,36 @@ def test_every_split_against_oracle(torch_cuda, fdas, split):
     plan.close()
 
 
+def test_every_tap_count_against_oracle(torch_cuda, fdas):
+    """One template of each tap count 1..100 (every padding of every step
+    count 1..6 on the direct route; 97..100 stay on overlap-save), all that
+    can go direct run directly, 20011 points."""
+    m = 100
+    _, bank = datagen.random_case(31, 8, m, m)
+    rng = np.random.Generator(np.random.PCG64(32))
+    tl = np.arange(1, m + 1, dtype=np.int32)
+    rng.shuffle(tl)
+    taps = np.zeros_like(bank.taps)
+    for t in range(m):
+        v = rng.standard_normal(2 * int(tl[t]))
+        taps[t, :tl[t]] = (v[0::2] + 1j * v[1::2]) / np.sqrt(2.0 * tl[t])
+    bank = datagen.Bank(np.zeros(m), taps, tl)
+    n = 20011
+    x, _ = datagen.random_case(33, n, 1, 1)
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n, seg_fft=1024)
+    plan.set_direct_templates(m)
+    assert plan.info.direct_templates == 96
+    P = plane(torch_cuda, plan, x)
+    st = against_oracle(P, x, bank, n)
+    _say(st.summary())
+    assert st.norm_err <= FP32_TOL
+    # each row on its own peak as well: short templates have small powers
+    ref = oracle.power(x, bank.taps, bank.tap_len)
+    for t in range(m):
+        assert np.abs(P[t] - ref[t]).max() <= FP32_TOL * ref[t].max(), (t, int(tl[t]))
+    plan.close()
+
+
 def test_rows_are_bitwise_stable_across_splits(torch_cuda, fdas):
     """A template's row depends only on the route that computes it: the first
     block is the same with 8 or 16 direct templates, and every template on
