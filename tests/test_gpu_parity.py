@@ -147,6 +147,34 @@ def test_edge_cases(torch_cuda, fdas, seed, n, m, k_max, L, method):
     assert st.norm_err <= FP32_TOL, st.summary()
 
 
+@pytest.mark.parametrize("method", ["convolve", "tdfir"])
+def test_every_tap_count_up_to_half_the_segment(torch_cuda, fdas, method):
+    """One template of every tap count 1..512 at L = 1024 (up to K_max =
+    L / 2), the whole bank by overlap-save (direct route off) or by TDFIR,
+    12007 points, each row against the oracle on its own peak."""
+    m = 512
+    _, bank = datagen.random_case(41, 8, m, m)
+    rng = np.random.Generator(np.random.PCG64(42))
+    tl = np.arange(1, m + 1, dtype=np.int32)
+    rng.shuffle(tl)
+    taps = np.zeros_like(bank.taps)
+    for t in range(m):
+        v = rng.standard_normal(2 * int(tl[t]))
+        taps[t, :tl[t]] = (v[0::2] + 1j * v[1::2]) / np.sqrt(2.0 * tl[t])
+    bank = datagen.Bank(np.zeros(m), taps, tl)
+    n = 12007
+    x, _ = datagen.random_case(43, n, 1, 1)
+    _say(f"[every tap count] 512 templates of 1..512 taps, n={n}, L=1024, {method}")
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n, seg_fft=1024)
+    plan.set_direct_templates(0)
+    P = run_plane(torch_cuda, plan, x, method)
+    ref = oracle.power(x, bank.taps, bank.tap_len)
+    worst = max(float(np.abs(P[t] - ref[t]).max() / ref[t].max()) for t in range(m))
+    _say(f"  worst row error / its peak {worst:.3e}")
+    assert worst <= FP32_TOL
+    plan.close()
+
+
 def test_prefix_length_and_zero_template(torch_cuda, fdas):
     """n < input_len, and a template with zero taps gives an all-zero row."""
     x, bank = datagen.random_case(9, 30000, 4, 40)
