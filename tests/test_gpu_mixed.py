@@ -134,6 +134,35 @@ def test_mixed_cases(torch_cuda, fdas, prec, seed, n, m, k_max):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_every_tap_count(torch_cuda, fdas, prec):
+    """One template of every tap count 1..1024 (up to L / 2), 12007 points:
+    each row against the oracle on the stored input, on its own peak (the
+    template spectra share one power-of-two scale, so short templates meet
+    the matrix cores with small operands)."""
+    torch = torch_cuda
+    m = 1024
+    _, bank = datagen.random_case(51, 8, m, m)
+    rng = np.random.Generator(np.random.PCG64(52))
+    tl = np.arange(1, m + 1, dtype=np.int32)
+    rng.shuffle(tl)
+    taps = np.zeros_like(bank.taps)
+    for t in range(m):
+        v = rng.standard_normal(2 * int(tl[t]))
+        taps[t, :tl[t]] = (v[0::2] + 1j * v[1::2]) / np.sqrt(2.0 * tl[t])
+    bank = datagen.Bank(np.zeros(m), taps, tl)
+    n = 12007
+    x, _ = datagen.random_case(53, n, 1, 1)
+    _say(f"[mixed every tap count] {prec}: 1024 templates of 1..1024 taps, n={n}")
+    plan = fdas.Plan(bank.taps, bank.tap_len, input_len=n, seg_fft=2048, precision=prec)
+    P = run16(torch, plan, x, prec)
+    ref = oracle.power(stored(torch, x, prec), bank.taps, bank.tap_len)
+    worst = max(float(np.abs(P[t] - ref[t]).max() / ref[t].max()) for t in range(m))
+    _say(f"  worst row error / its peak {worst:.3e}")
+    assert worst <= MIXED_TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_mixed_toy(torch_cuda, fdas, toy, prec):
     _say(f"[mixed toy] 9 x 2^16 {prec}")
     plan = fdas.Plan(toy.bank.taps, toy.bank.tap_len, input_len=toy.n, seg_fft=2048, precision=prec)
