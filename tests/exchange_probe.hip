@@ -10,7 +10,8 @@
 // and applying it twice gives the input back.
 //   method 0: through LDS, each lane writing its 16 values and reading 16,
 //             laid out as the segment transform lays out this exchange
-//             (slot k1 * 65 + r * 4 + p), two barriers per exchange;
+//             (slot k1 * 65 + r * 4 + p); the workgroup is one wave, so the
+//             barriers compile to waits on its own LDS accesses;
 //   method 1: v_permlane32_swap then v_permlane16_swap on register pairs,
 //             four swaps per g and component (32 per exchange), no LDS.
 // Each wave runs `reps` exchanges, adding 1 to v[0] after each, and writes
